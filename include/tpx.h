@@ -1,0 +1,196 @@
+/*
+ * tpx.h -- C ABI of the MI355X (gfx950) TimePix3 VMI hot path.
+ *
+ * The library turns a stream of 64-bit TimePix3 packets into particle hits:
+ * it decodes pixel and trigger words, unwraps their counters, assigns each
+ * pixel to its laser shot with a time-of-flight cut, groups the pixels of a
+ * shot into hits by space-time connectivity and reduces every hit to a
+ * ToT-weighted centroid (x, y, ToF).  Method: arXiv 2603.04942, "Fast
+ * array-based particle coincidence detection in a TimePix3-based velocity map
+ * imaging instrument" (Sec. III data stream, Sec. IV preprocessing, Sec. V
+ * centroiding).  Every step runs in HIP kernels on the device.
+ *
+ * Conventions for every entry point:
+ *  - Pointers are HIP device pointers unless the parameter name ends in _h
+ *    (host).  The caller owns every buffer; only tpx_stream_create allocates.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *    work is ordered on it.  A call that returns a count through a _h pointer
+ *    synchronises `stream` before returning (these are the only sync points).
+ *  - No exception crosses the ABI.  On error the call returns a negative
+ *    status, outputs are unspecified, state objects are left unchanged, and
+ *    tpx_last_error() describes the failure.  TPX_ECAPACITY stores the
+ *    required element count into the corresponding _h count, so the call can
+ *    be retried with a larger buffer.  Argument errors (TPX_EINVAL) are
+ *    detected before any kernel is launched; malformed input values inside
+ *    device buffers are detected on the device and reported after the sync.
+ *  - Times are integer ticks of 1.5625 ns (25/16 ns, i.e. 256 of the chip's
+ *    25/4096 ns units, Sec. IV).  ToT is in 25 ns counts.
+ *  - Thread safety: distinct tpx_stream objects may be used concurrently from
+ *    different host threads on different HIP streams; one object must not be
+ *    used by two calls at once.
+ */
+#ifndef TPX_H
+#define TPX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t tpx_status;
+#define TPX_OK 0
+#define TPX_EINVAL (-1)    /* bad argument or malformed input values          */
+#define TPX_ECAPACITY (-2) /* an output buffer is too small (see _h count)    */
+#define TPX_ESTREAM (-3)   /* triggers go back in time, or a wrap count < 0   */
+#define TPX_EHIP (-4)      /* a HIP runtime call failed                       */
+#define TPX_ENOMEM (-5)    /* device allocation failed (tpx_stream_create)    */
+#define TPX_EINTERNAL (-6) /* an internal consistency check failed            */
+
+/* Processing parameters (Sec. IV and Sec. V).  Fill with tpx_params_default
+ * and override fields.  Limits are checked on every call (TPX_EINVAL). */
+typedef struct {
+    uint32_t dxy;           /* spatial radius r of the neighbourhood, Chebyshev
+                               distance, inclusive (Eq. 4); 1 = 8-connected.
+                               0..7                                            */
+    uint32_t dt_ticks;      /* time radius r_t, |dToA| <= dt_ticks (Eq. 4 on
+                               the ToF axis); 128 = 200 ns.  0..65535          */
+    uint32_t tof_max_ticks; /* keep a pixel when ToF <= this (Sec. IV, 100 us
+                               = 64000).  1..2^30-1                            */
+    uint32_t trig_subtype;  /* TDC subtype nibble that marks a laser trigger;
+                               0xF = TDC1 rising edge                          */
+    uint64_t jump_ticks;    /* unwrap threshold (Sec. IV, 20 s = 1.28e10).
+                               Must be below both wrap periods                 */
+    int64_t pix_epoch0;     /* pixel-counter wraps before the first pixel word */
+    int64_t tdc_epoch0;     /* trigger-counter wraps before the first trigger  */
+    uint64_t close_slack_ticks; /* streaming: shot s is closed once trigger s+1
+                               has been seen and a pixel later than T[s] +
+                               tof_max + slack has arrived (default 64000)     */
+    const float* walk_lut_ns;   /* NULL, or 1024 device floats Delta ToF(ToT)
+                               in ns subtracted from each pixel's ToF before
+                               the time centroid (Eq. 1).  Default NULL.       */
+} tpx_params;
+
+void tpx_params_default(tpx_params* p_h);
+
+/* Decoded pixel events, structure of arrays (device pointers).  `shot`
+ * indexes the trigger table that came with the events; `toa` is the unwrapped
+ * arrival tick. */
+typedef struct {
+    uint16_t* x;   /* 0..255 */
+    uint16_t* y;   /* 0..255 */
+    uint16_t* tot; /* 0..1023 */
+    uint32_t* shot;
+    uint64_t* toa;
+} tpx_events;
+
+/* One particle hit (Eq. 8-9 over one connected component).  48 bytes. */
+typedef struct {
+    float x, y;         /* ToT-weighted centroid in pixels (pixel centres at
+                           integer coordinates)                               */
+    float tof_ns;       /* ToT-weighted mean ToF in ns after the shot trigger */
+    uint32_t npix;      /* pixels in the hit                                  */
+    uint64_t shot;      /* shot (trigger) index                               */
+    uint64_t label;     /* smallest event index in the hit                    */
+    uint64_t toa_first; /* earliest unwrapped ToA in the hit, ticks           */
+    uint32_t tot_sum;   /* sum of ToT                                          */
+    uint32_t flags;     /* bit 0: sum of ToT was 0, plain means were used     */
+} tpx_hit;
+
+typedef struct {
+    uint64_t n_packets, n_pixels, n_tdc, n_other, n_pre_trigger, n_tof_cut,
+        n_events, n_hits, n_pix_wraps, n_pix_backjumps, n_tdc_wraps,
+        n_tdc_backjumps, n_late_drop;
+} tpx_stats;
+
+/* Unwrap and trigger state carried between tpx_decode calls on consecutive
+ * pieces of one stream.  Initialise with tpx_unwrap_state_init. */
+typedef struct {
+    int64_t pix_epoch, tdc_epoch;  /* wraps in force                          */
+    uint64_t pix_last_raw, tdc_last_raw;
+    uint32_t pix_has_last, tdc_has_last;
+    uint64_t trig_base;            /* global index of the next trigger        */
+    uint64_t last_trig_toa;        /* unwrapped time of trigger trig_base-1   */
+    uint32_t has_last_trig, pad;
+} tpx_unwrap_state;
+
+void tpx_unwrap_state_init(tpx_unwrap_state* st_h, const tpx_params* p_h);
+
+/* Device workspace needed by tpx_decode / tpx_cluster / tpx_centroid for up
+ * to max_packets packets or max_events events.  The workspace holds only
+ * transient data; its contents need not be preserved between calls. */
+size_t tpx_workspace_bytes(size_t max_packets, size_t max_events);
+
+/* Decode, unwrap and assign (Sec. III; Sec. IV, ToA Unwrapping and
+ * Eliminating Background Counts).
+ *  pkts[n_pkts]   device, 64-bit words in stream order.
+ *  st_h           in: state before pkts[0]; out (on success): after.
+ *  ev, ev_cap     kept pixels in stream order; ev.shot = global trigger index
+ *                 (st_h->trig_base + k for the k-th trigger of this call, or
+ *                 trig_base-1 for pixels after the previous call's last one).
+ *  trig_toa       the unwrapped triggers of this call, trig_cap entries.
+ *  n_ev_h, n_trig_h, stats_h  host outputs (stats_h may be NULL).
+ * Pixels before any trigger are dropped (n_pre_trigger); pixels whose ToF
+ * exceeds tof_max_ticks are dropped (n_tof_cut).  TPX_ESTREAM when triggers go
+ * back in time or a wrap count would become negative. */
+tpx_status tpx_decode(const uint64_t* pkts, size_t n_pkts, const tpx_params* p_h,
+                      tpx_unwrap_state* st_h, tpx_events ev, size_t ev_cap,
+                      uint64_t* trig_toa, size_t trig_cap, size_t* n_ev_h,
+                      size_t* n_trig_h, tpx_stats* stats_h, void* ws,
+                      size_t ws_bytes, void* stream);
+
+/* Group events into hits (Sec. V, Neighborhoods, Eqs. 3-5, closed
+ * transitively): i and j are connected when ev.shot[i] == ev.shot[j],
+ * |x_i - x_j| <= dxy, |y_i - y_j| <= dxy and |toa_i - toa_j| <= dt_ticks.
+ * labels[i] = the smallest index j connected to i (events need not be sorted
+ * by shot).  n_clusters_h (may be NULL) = number of hits. */
+tpx_status tpx_cluster(tpx_events ev, size_t n_ev, const tpx_params* p_h,
+                       uint32_t* labels, size_t* n_clusters_h, void* ws,
+                       size_t ws_bytes, void* stream);
+
+/* ToT-weighted centroids (Sec. V, Centroiding, Eqs. 8-9) of the hits given by
+ * `labels` (as produced by tpx_cluster: labels[i] is the smallest index of i's
+ * hit).  ToF = toa - trig_toa[shot].  Hits come out in (shot, label) order. */
+tpx_status tpx_centroid(tpx_events ev, const uint32_t* labels, size_t n_ev,
+                        const uint64_t* trig_toa, size_t n_trig,
+                        const tpx_params* p_h, tpx_hit* hits, size_t hit_cap,
+                        size_t* n_hits_h, void* ws, size_t ws_bytes,
+                        void* stream);
+
+/* Streaming: decode -> cluster -> centroid over consecutive chunks of one
+ * packet stream, carrying unwrap state and the pixels of shots that are still
+ * open across chunk boundaries.  Hit labels are global kept-pixel indices in
+ * stream order; hit shots are global trigger indices. */
+typedef struct tpx_stream tpx_stream;
+
+/* Allocates device memory for chunks of up to max_chunk_pkts packets. */
+tpx_status tpx_stream_create(const tpx_params* p_h, size_t max_chunk_pkts,
+                             tpx_stream** out_h);
+
+/* Process one chunk.  Hits of every shot closed by this chunk (all shots when
+ * flush != 0) are written in (shot, label) order.  A pixel that belongs to a
+ * shot closed by an earlier chunk is counted in n_late_drop. */
+tpx_status tpx_process_stream(tpx_stream* s, const uint64_t* chunk,
+                              size_t n_pkts, int flush, tpx_hit* hits,
+                              size_t hit_cap, size_t* n_hits_h,
+                              tpx_stats* stats_h, void* stream);
+
+/* Checkpoint: serialise the stream state (unwrap state, trigger window, open
+ * shots' pixels) into a host buffer.  With buf_h == NULL only the size is
+ * returned in *bytes_h. */
+tpx_status tpx_stream_get_state(const tpx_stream* s, void* buf_h, size_t* bytes_h);
+tpx_status tpx_stream_set_state(tpx_stream* s, const void* buf_h, size_t bytes);
+void tpx_stream_destroy(tpx_stream* s);
+
+/* Diagnostics: number of chunks of this stream whose kept pixels were not in
+ * shot order and took the general (sorting) path. */
+uint64_t tpx_stream_fallback_count(const tpx_stream* s);
+
+const char* tpx_status_str(tpx_status st);
+const char* tpx_last_error(void); /* thread-local detail of the last failure */
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TPX_H */

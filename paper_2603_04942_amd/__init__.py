@@ -1,0 +1,321 @@
+"""Python binding of libtpx, the MI355X (gfx950) TimePix3 VMI hot path.
+
+Argument marshalling only: every step of the method (decode, unwrap, shot
+assignment, clustering, centroids) runs in the library's HIP kernels, reached
+through the C ABI declared in include/tpx.h.  PyTorch supplies device memory
+and the current HIP stream.  There is no CPU fallback: if libtpx.so is missing
+or no GPU is visible, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtpx.so")
+
+OK, EINVAL, ECAPACITY, ESTREAM, EHIP, ENOMEM, EINTERNAL = 0, -1, -2, -3, -4, -5, -6
+
+
+class TpxError(RuntimeError):
+    def __init__(self, rc, what, detail=""):
+        super().__init__(f"{what}: status {rc} ({detail})")
+        self.rc = rc
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("dxy", ctypes.c_uint32), ("dt_ticks", ctypes.c_uint32),
+                ("tof_max_ticks", ctypes.c_uint32), ("trig_subtype", ctypes.c_uint32),
+                ("jump_ticks", ctypes.c_uint64), ("pix_epoch0", ctypes.c_int64),
+                ("tdc_epoch0", ctypes.c_int64), ("close_slack_ticks", ctypes.c_uint64),
+                ("walk_lut_ns", ctypes.c_void_p)]
+
+
+class Events(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("tot", ctypes.c_void_p),
+                ("shot", ctypes.c_void_p), ("toa", ctypes.c_void_p)]
+
+
+STAT_FIELDS = ("n_packets", "n_pixels", "n_tdc", "n_other", "n_pre_trigger", "n_tof_cut",
+               "n_events", "n_hits", "n_pix_wraps", "n_pix_backjumps", "n_tdc_wraps",
+               "n_tdc_backjumps", "n_late_drop")
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_uint64) for f in STAT_FIELDS]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f in STAT_FIELDS}
+
+
+class UnwrapState(ctypes.Structure):
+    _fields_ = [("pix_epoch", ctypes.c_int64), ("tdc_epoch", ctypes.c_int64),
+                ("pix_last_raw", ctypes.c_uint64), ("tdc_last_raw", ctypes.c_uint64),
+                ("pix_has_last", ctypes.c_uint32), ("tdc_has_last", ctypes.c_uint32),
+                ("trig_base", ctypes.c_uint64), ("last_trig_toa", ctypes.c_uint64),
+                ("has_last_trig", ctypes.c_uint32), ("pad", ctypes.c_uint32)]
+
+
+HIT_DTYPE = np.dtype([("x", "<f4"), ("y", "<f4"), ("tof_ns", "<f4"), ("npix", "<u4"),
+                      ("shot", "<u8"), ("label", "<u8"), ("toa_first", "<u8"),
+                      ("tot_sum", "<u4"), ("flags", "<u4")])
+assert HIT_DTYPE.itemsize == 48
+
+EXPORTS = ("tpx_params_default", "tpx_unwrap_state_init", "tpx_workspace_bytes", "tpx_decode",
+           "tpx_cluster", "tpx_centroid", "tpx_stream_create", "tpx_process_stream",
+           "tpx_stream_get_state", "tpx_stream_set_state", "tpx_stream_destroy",
+           "tpx_status_str", "tpx_last_error", "tpx_stream_fallback_count")
+
+_lib = None
+
+
+def load(path=LIB_PATH):
+    """Load libtpx.so and declare its signatures (no GPU needed for this)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with paper_2603_04942_amd/build.py")
+    lib = ctypes.CDLL(path)
+    P, S, I = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32
+    lib.tpx_params_default.argtypes = [P]
+    lib.tpx_params_default.restype = None
+    lib.tpx_unwrap_state_init.argtypes = [P, P]
+    lib.tpx_unwrap_state_init.restype = None
+    lib.tpx_workspace_bytes.argtypes = [S, S]
+    lib.tpx_workspace_bytes.restype = S
+    lib.tpx_decode.argtypes = [P, S, P, P, Events, S, P, S, P, P, P, P, S, P]
+    lib.tpx_cluster.argtypes = [Events, S, P, P, P, P, S, P]
+    lib.tpx_centroid.argtypes = [Events, P, S, P, S, P, P, S, P, P, S, P]
+    lib.tpx_stream_create.argtypes = [P, S, P]
+    lib.tpx_process_stream.argtypes = [P, P, S, ctypes.c_int, P, S, P, P, P]
+    lib.tpx_stream_get_state.argtypes = [P, P, P]
+    lib.tpx_stream_set_state.argtypes = [P, P, S]
+    lib.tpx_stream_destroy.argtypes = [P]
+    lib.tpx_stream_destroy.restype = None
+    lib.tpx_status_str.argtypes = [I]
+    lib.tpx_status_str.restype = ctypes.c_char_p
+    lib.tpx_last_error.argtypes = []
+    lib.tpx_last_error.restype = ctypes.c_char_p
+    lib.tpx_stream_fallback_count.argtypes = [P]
+    lib.tpx_stream_fallback_count.restype = ctypes.c_uint64
+    for f in ("tpx_decode", "tpx_cluster", "tpx_centroid", "tpx_stream_create",
+              "tpx_process_stream", "tpx_stream_get_state", "tpx_stream_set_state"):
+        getattr(lib, f).restype = I
+    _lib = lib
+    return lib
+
+
+def _check(rc, what):
+    if rc != OK:
+        lib = load()
+        raise TpxError(rc, what, lib.tpx_last_error().decode())
+
+
+def make_params(**kw):
+    """tpx_params with the library defaults, overridden by keyword."""
+    lib = load()
+    p = Params()
+    lib.tpx_params_default(ctypes.byref(p))
+    walk = kw.pop("walk_lut_ns", None)
+    for k, v in kw.items():
+        setattr(p, k, v)
+    if walk is not None:
+        p.walk_lut_ns = walk.data_ptr()
+    return p
+
+
+# ---------------------------------------------------------------- torch glue
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("libtpx needs a visible GPU (no CPU fallback)")
+    return torch
+
+
+def _stream(torch):
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _dev(torch, a, dtype):
+    if isinstance(a, torch.Tensor):
+        return a.to(device="cuda", dtype=dtype).contiguous()
+    return torch.from_numpy(np.ascontiguousarray(a)).view(dtype).to("cuda")
+
+
+def _u64(torch, a):
+    if isinstance(a, torch.Tensor):
+        return a.to("cuda").contiguous().view(torch.int64)
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint64).view(np.int64)).to("cuda")
+
+
+def events_struct(ev):
+    return Events(ev["x"].data_ptr(), ev["y"].data_ptr(), ev["tot"].data_ptr(),
+                  ev["shot"].data_ptr(), ev["toa"].data_ptr())
+
+
+def to_device_events(ev):
+    """numpy/torch dict (x, y, tot u16; shot u32; toa u64) -> device tensors."""
+    torch = _torch()
+    return dict(x=_dev(torch, np.asarray(ev["x"], np.uint16).view(np.int16), torch.int16),
+                y=_dev(torch, np.asarray(ev["y"], np.uint16).view(np.int16), torch.int16),
+                tot=_dev(torch, np.asarray(ev["tot"], np.uint16).view(np.int16), torch.int16),
+                shot=_dev(torch, np.asarray(ev["shot"], np.uint32).view(np.int32), torch.int32),
+                toa=_u64(torch, np.asarray(ev["toa"], np.uint64)))
+
+
+def hits_to_numpy(h, n):
+    return h[:n].cpu().numpy().view(HIT_DTYPE).reshape(-1)
+
+
+def workspace(n_packets, n_events):
+    torch = _torch()
+    nbytes = load().tpx_workspace_bytes(n_packets, n_events)
+    return torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+
+
+def decode(packets, state=None, params=None, ev_cap=None, trig_cap=None, ws=None):
+    """tpx_decode over one buffer of packets (device tensor or numpy uint64).
+    Returns (events dict of device tensors, triggers, stats dict, state)."""
+    torch = _torch()
+    lib = load()
+    pk = _u64(torch, packets)
+    n = pk.numel()
+    p = params or make_params()
+    st = state or UnwrapState()
+    if state is None:
+        lib.tpx_unwrap_state_init(ctypes.byref(st), ctypes.byref(p))
+    ev_cap = n if ev_cap is None else ev_cap
+    trig_cap = n if trig_cap is None else trig_cap
+    ev = dict(x=torch.empty(ev_cap, dtype=torch.int16, device="cuda"),
+              y=torch.empty(ev_cap, dtype=torch.int16, device="cuda"),
+              tot=torch.empty(ev_cap, dtype=torch.int16, device="cuda"),
+              shot=torch.empty(ev_cap, dtype=torch.int32, device="cuda"),
+              toa=torch.empty(ev_cap, dtype=torch.int64, device="cuda"))
+    trig = torch.empty(max(trig_cap, 1), dtype=torch.int64, device="cuda")
+    ws = workspace(n, 0) if ws is None else ws
+    ne, nt = ctypes.c_size_t(), ctypes.c_size_t()
+    stats = Stats()
+    rc = lib.tpx_decode(_ptr(pk), n, ctypes.byref(p), ctypes.byref(st), events_struct(ev), ev_cap,
+                        _ptr(trig), trig_cap, ctypes.byref(ne), ctypes.byref(nt),
+                        ctypes.byref(stats), _ptr(ws), ws.numel(), _stream(torch))
+    if rc == ECAPACITY:
+        raise TpxError(rc, "tpx_decode", f"need {ne.value} events / {nt.value} triggers")
+    _check(rc, "tpx_decode")
+    ev = {k: v[:ne.value] for k, v in ev.items()}
+    return ev, trig[:nt.value], stats.as_dict(), st
+
+
+def cluster(ev, params=None, ws=None):
+    """tpx_cluster: labels (int32 tensor; values are uint32 event indices)."""
+    torch = _torch()
+    lib = load()
+    n = ev["x"].numel()
+    p = params or make_params()
+    labels = torch.empty(max(n, 1), dtype=torch.int32, device="cuda")
+    ws = workspace(0, n) if ws is None else ws
+    nc = ctypes.c_size_t()
+    rc = lib.tpx_cluster(events_struct(ev), n, ctypes.byref(p), _ptr(labels), ctypes.byref(nc),
+                         _ptr(ws), ws.numel(), _stream(torch))
+    _check(rc, "tpx_cluster")
+    return labels[:n], int(nc.value)
+
+
+def centroid(ev, labels, trig, params=None, hit_cap=None, ws=None):
+    """tpx_centroid: numpy structured array of hits (HIT_DTYPE)."""
+    torch = _torch()
+    lib = load()
+    n = ev["x"].numel()
+    p = params or make_params()
+    trig = _u64(torch, trig)
+    hit_cap = n if hit_cap is None else hit_cap
+    hits = torch.empty((max(hit_cap, 1), 48), dtype=torch.uint8, device="cuda")
+    ws = workspace(0, n) if ws is None else ws
+    nh = ctypes.c_size_t()
+    rc = lib.tpx_centroid(events_struct(ev), _ptr(labels), n, _ptr(trig), trig.numel(),
+                          ctypes.byref(p), _ptr(hits), hit_cap, ctypes.byref(nh), _ptr(ws),
+                          ws.numel(), _stream(torch))
+    if rc == ECAPACITY:
+        raise TpxError(rc, "tpx_centroid", f"need {nh.value} hits")
+    _check(rc, "tpx_centroid")
+    return hits_to_numpy(hits, nh.value)
+
+
+class Stream:
+    """tpx_stream: decode -> cluster -> centroid over consecutive chunks."""
+
+    def __init__(self, max_chunk_pkts, params=None, **kw):
+        self.torch = _torch()
+        self.lib = load()
+        self.params = params or make_params(**kw)
+        self._walk = kw.get("walk_lut_ns")
+        h = ctypes.c_void_p()
+        _check(self.lib.tpx_stream_create(ctypes.byref(self.params), max_chunk_pkts,
+                                          ctypes.byref(h)), "tpx_stream_create")
+        self.h = h
+        self.max_chunk = max_chunk_pkts
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.tpx_stream_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def process_raw(self, chunk, flush, hits, hit_cap):
+        """Device-only call: chunk and hits are device tensors; returns
+        (status, n_hits, stats) without copying anything back."""
+        nh = ctypes.c_size_t()
+        st = Stats()
+        rc = self.lib.tpx_process_stream(self.h, _ptr(chunk), chunk.numel(), int(flush),
+                                         _ptr(hits), hit_cap, ctypes.byref(nh), ctypes.byref(st),
+                                         _stream(self.torch))
+        return rc, int(nh.value), st
+
+    def process(self, chunk, flush=False, hit_cap=None, hits=None):
+        torch = self.torch
+        pk = _u64(torch, chunk)
+        if hits is None:
+            hit_cap = max(pk.numel(), 1024) if hit_cap is None else hit_cap
+            hits = torch.empty((hit_cap, 48), dtype=torch.uint8, device="cuda")
+        else:
+            hit_cap = hits.shape[0]
+        rc, n, st = self.process_raw(pk, flush, hits, hit_cap)
+        if rc == ECAPACITY:
+            raise TpxError(rc, "tpx_process_stream", f"need {n} hits")
+        _check(rc, "tpx_process_stream")
+        return hits_to_numpy(hits, n), st.as_dict()
+
+    def get_state(self):
+        n = ctypes.c_size_t()
+        _check(self.lib.tpx_stream_get_state(self.h, None, ctypes.byref(n)), "get_state")
+        buf = ctypes.create_string_buffer(n.value)
+        _check(self.lib.tpx_stream_get_state(self.h, buf, ctypes.byref(n)), "get_state")
+        return bytes(buf.raw[:n.value])
+
+    def set_state(self, blob):
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        _check(self.lib.tpx_stream_set_state(self.h, buf, len(blob)), "set_state")
+
+    @property
+    def fallback_count(self):
+        return int(self.lib.tpx_stream_fallback_count(self.h))
+
+
+def process_stream(packets, flush=True, **kw):
+    """One-shot helper: the whole packet buffer as a single flushed chunk."""
+    s = Stream(max(int(len(packets)), 1), **kw)
+    try:
+        return s.process(packets, flush=flush)
+    finally:
+        s.close()

@@ -1,0 +1,124 @@
+// Kernel argument blocks and launch wrappers of libtpx (internal).
+#pragma once
+
+#include "tpx_internal.h"
+
+namespace tpx {
+
+struct AssignArgs {
+    const uint64_t* pk;
+    uint64_t n;
+    uint32_t sub;
+    uint32_t tof_max;
+    uint64_t jump;
+    const TileEntry* entries;
+    const uint64_t* tab;       // trigger table: [window triggers..., new triggers...]
+    uint64_t n_win;            // window triggers in front of this call's
+    const unsigned long long* n_trig_dev;  // triggers decoded by this call
+    uint64_t first_open;       // table index of the first shot still open
+    uint64_t tab_has_before;   // triggers existed before tab[0]
+    // packed output (stream path)
+    uint64_t* ev;
+    uint64_t ev_off;           // events already in front of this chunk's (carry)
+    uint64_t ev_cap;
+    uint32_t* shot_out;        // optional: table index of every kept event
+    uint32_t* shot_cnt;        // kept events per table index (stream path)
+    // structure-of-arrays output (tpx_decode)
+    tpx_events soa;
+    uint64_t shot_base;        // global index of tab[0]
+    TileRec* recs;
+    uint64_t* lb_status;       // zeroed, one word per tile
+    DevResults* res;
+};
+
+struct ClusterArgs {
+    const uint64_t* ev;        // packed events in group order (stream path)
+    tpx_events soa;            // original events (event mode)
+    const uint32_t* perm;      // group-order position -> original position, or null
+    const uint32_t* grp_off;   // first position of each group, [n_grp + 1]
+    const uint32_t* grp_shot;  // group -> table index (stream) or shot value; null = identity
+    const unsigned long long* n_ev_dev;
+    const unsigned long long* n_grp_dev;
+    uint32_t q;                // segment stride in events
+    uint32_t dxy, dt;
+    const uint64_t* carry_gidx;
+    uint64_t n_carry, ev_base;
+    const uint64_t* tab;
+    uint64_t tab_base;
+    const float* walk;
+    tpx_hit* hits;
+    uint64_t hit_cap;
+    uint32_t* labels;
+    uint64_t* lb_status;       // zeroed, one word per segment
+    DevResults* res;
+    const unsigned long long* skip;  // non-zero: do nothing (events not in shot order)
+    // per-event scratch for segments that do not fit in LDS
+    uint32_t *g_parent, *g_chain, *g_next, *g_t, *g_sl, *g_xy;
+    uint64_t* g_acc;           // 6 words per event
+};
+
+void launch_tile_summary(const uint64_t* pk, uint64_t n, uint32_t sub, uint64_t jump,
+                         TileSum* sums, uint64_t* tdc_slot, uint32_t* tdc_cnt, hipStream_t s);
+void launch_tile_scan(const TileSum* sums, const uint32_t* tdc_cnt, uint64_t ntiles, RunSum pix0,
+                      RunSum tdc0, int64_t pe0, int64_t te0, uint64_t jump, TileEntry* entries,
+                      DevResults* res, hipStream_t s);
+void launch_trig_unwrap(const TileEntry* entries, const uint32_t* tdc_cnt, const uint64_t* slot,
+                        uint64_t ntiles, uint64_t jump, uint64_t* tab, DevResults* res,
+                        hipStream_t s);
+void launch_assign(const AssignArgs& a, bool soa, hipStream_t s);
+void launch_cluster(const ClusterArgs& a, bool event_mode, uint64_t grid, hipStream_t s);
+// workgroups needed to cover every segment of up to max_events events
+uint64_t cluster_grid(uint64_t max_events, uint32_t q);
+int cluster_capacity();
+
+// utilities (tpx_util.hip)
+void launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
+void launch_fill_u64(uint64_t* p, uint64_t v, uint64_t n, hipStream_t s);
+// out[0..n] = exclusive prefix of in[0..n), out[n] = total; n = *n_dev if n_dev
+void launch_scan_u32(const uint32_t* in, uint32_t* out, uint64_t n_host,
+                     const unsigned long long* n_dev, uint32_t* block_tmp, hipStream_t s);
+void launch_tiles_sorted(const TileRec* recs, uint64_t ntiles, uint64_t carry_last_plus1,
+                         DevResults* res, hipStream_t s);
+void launch_close(const uint64_t* tab, const unsigned long long* n_trig_dev, uint64_t n_win,
+                  uint64_t first_open, int flush, uint64_t max_t_plus1_prev, uint64_t tof_max,
+                  uint64_t slack, const uint32_t* shot_off, DevResults* res, hipStream_t s);
+void launch_set_rows(DevResults* res, uint64_t n_win, hipStream_t s);
+void launch_check_events(tpx_events ev, uint64_t n, DevResults* res, hipStream_t s);
+// groups of equal keys in a sorted key array: grp_off[G+1], grp_shot[G], res->n_groups = G
+void launch_boundaries(const uint32_t* sorted_key, uint64_t n, uint32_t* flags, uint32_t* scan,
+                       uint32_t* block_tmp, uint32_t* grp_off, uint32_t* grp_shot,
+                       DevResults* res, hipStream_t s);
+// fallback stream path: closed groups / events from sorted keys and the close index
+void launch_close_sorted(const uint32_t* sorted_key, uint64_t n, const uint32_t* grp_shot,
+                         DevResults* res, hipStream_t s);
+void radix_sort_pairs(uint32_t* key, uint32_t* val, uint32_t* key2, uint32_t* val2,
+                      uint32_t* flags, uint32_t* scan, uint32_t* block_tmp, uint64_t n, int bits,
+                      hipStream_t s, uint32_t** key_out, uint32_t** val_out);
+void launch_iota_u32(uint32_t* p, uint64_t n, hipStream_t s);
+void launch_gather_keys(const uint32_t* shot, const uint32_t* perm, uint32_t* out, uint64_t n,
+                        hipStream_t s);
+void launch_gather_packed(const uint64_t* ev, const uint32_t* perm, uint64_t* out, uint64_t n,
+                          hipStream_t s);
+void launch_carry_in(const uint64_t* c_ev, const uint32_t* c_shot, uint64_t n_carry,
+                     uint32_t rebase, uint64_t* ev, uint32_t* shot_arr, uint32_t* shot_cnt,
+                     hipStream_t s);
+void launch_carry_out(const uint64_t* ev, const uint32_t* perm, const uint32_t* shot_arr,
+                      const uint32_t* shot_off, const unsigned long long* n_rows_dev,
+                      const unsigned long long* n_close_ev, const unsigned long long* n_kept,
+                      const uint64_t* carry_gidx_in, uint64_t n_carry, uint64_t ev_base,
+                      uint64_t* c_ev, uint32_t* c_shot, uint64_t* c_gidx, uint64_t carry_cap,
+                      DevResults* res, hipStream_t s);
+void launch_copy_u64(const uint64_t* src, uint64_t* dst, uint64_t n, hipStream_t s);
+// centroids of given labels (tpx_centroid)
+void launch_cent_init(uint64_t* acc, uint64_t n, hipStream_t s);
+void launch_cent_accum(tpx_events ev, const uint32_t* labels, uint64_t n, const uint64_t* trig,
+                       uint64_t n_trig, const float* walk, uint64_t* acc, DevResults* res,
+                       hipStream_t s);
+void launch_root_flags(const uint32_t* labels, uint64_t n, uint32_t* flags, hipStream_t s);
+void launch_compact_roots(const uint32_t* flags, const uint32_t* scan, uint64_t n,
+                          uint32_t* roots, hipStream_t s);
+void launch_cent_emit(tpx_events ev, const uint32_t* order, uint64_t n_roots,
+                      const uint64_t* acc, const uint64_t* trig, const float* walk,
+                      tpx_hit* hits, uint64_t hit_cap, hipStream_t s);
+
+}  // namespace tpx

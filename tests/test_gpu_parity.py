@@ -1,0 +1,241 @@
+"""Parity of the HIP path (through the C ABI) with the oracle on the same
+seeded inputs.  Integer results (events, triggers, labels, hit membership)
+must be bit-exact; centroids within 1e-4 px and 0.1 ns of the oracle's FP64
+values."""
+import dataclasses
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL_PX = 1e-4
+TOL_NS = 0.1
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def tpx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2603_04942_amd as t
+    t.load()
+    return t
+
+
+def _np_events(ev):
+    return dict(x=ev["x"].cpu().numpy().view(np.uint16), y=ev["y"].cpu().numpy().view(np.uint16),
+                tot=ev["tot"].cpu().numpy().view(np.uint16),
+                shot=ev["shot"].cpu().numpy().view(np.uint32),
+                toa=ev["toa"].cpu().numpy().view(np.uint64))
+
+
+def assert_hits_match(h, ref, tol_px=TOL_PX, tol_ns=TOL_NS):
+    assert h.size == ref.size, (h.size, ref.size)
+    for f in ("shot", "label", "npix", "tot_sum", "toa_first", "flags"):
+        a = h[f].astype(np.uint64)
+        b = ref[f].astype(np.uint64)
+        bad = np.nonzero(a != b)[0]
+        assert bad.size == 0, f"{f} differs at {bad[:5]}: {a[bad[:5]]} vs {b[bad[:5]]}"
+    for f, tol in (("x", tol_px), ("y", tol_px), ("tof_ns", tol_ns)):
+        d = np.abs(h[f].astype(np.float64) - ref[f])
+        assert d.max(initial=0) <= tol, f"{f}: max err {d.max()} at {np.argmax(d)}"
+
+
+# ------------------------------------------------------------------ decode
+@pytest.mark.parametrize("name,shots", [("c1", 1000), ("c2", 400), ("c3", 200)])
+def test_decode_parity(tpx, orc, name, shots):
+    _say(f"decode parity {name} shots={shots}")
+    w = synth.make_config(name, n_shots=shots)
+    kw = dict(pix_epoch0=w.pix_epoch0, tdc_epoch0=w.tdc_epoch0)
+    ref = orc.decode(w.packets, **kw)
+    ev, trig, stats, _ = tpx.decode(w.packets, params=tpx.make_params(**kw))
+    got = _np_events(ev)
+    for f in ("x", "y", "tot", "shot", "toa"):
+        assert np.array_equal(got[f], ref["events"][f]), f
+    assert np.array_equal(trig.cpu().numpy().view(np.uint64), ref["trig"])
+    for f in ("n_pixels", "n_tdc", "n_other", "n_pre_trigger", "n_tof_cut", "n_events",
+              "n_pix_wraps", "n_pix_backjumps", "n_tdc_wraps", "n_tdc_backjumps"):
+        assert stats[f] == ref["stats"][f], f
+
+
+def test_decode_across_wraps_and_calls(tpx, orc):
+    """Coincident pixel/trigger wrap inside shot 100; the stream is decoded
+    whole and in 7 pieces with the carried state; both equal the oracle."""
+    _say("decode across wraps")
+    W36 = 1 << 36
+    spec = dataclasses.replace(synth.SPECS["c1"], n_shots=200, seed=77,
+                               t0_ticks=W36 - 3000 - 100 * synth.SHOT_PERIOD_TICKS)
+    w = synth.generate(spec)
+    kw = dict(pix_epoch0=w.pix_epoch0, tdc_epoch0=w.tdc_epoch0)
+    ref = orc.decode(w.packets, **kw)
+    assert ref["stats"]["n_pix_backjumps"] >= 1
+    ev, trig, stats, _ = tpx.decode(w.packets, params=tpx.make_params(**kw))
+    got = _np_events(ev)
+    assert np.array_equal(got["toa"], ref["events"]["toa"])
+    assert np.array_equal(got["shot"], ref["events"]["shot"])
+    assert stats["n_pix_backjumps"] == ref["stats"]["n_pix_backjumps"]
+    # piecewise with carried state
+    cuts = np.sort(np.random.default_rng(5).choice(w.n_packets, 6, replace=False))
+    parts = np.split(w.packets, cuts)
+    st = None
+    evs, trigs = [], []
+    p = tpx.make_params(**kw)
+    for part in parts:
+        e, t, s, st = tpx.decode(part, state=st, params=p)
+        evs.append(_np_events(e))
+        trigs.append(t.cpu().numpy().view(np.uint64))
+    cat = {f: np.concatenate([e[f] for e in evs]) for f in evs[0]}
+    for f in ("x", "y", "tot", "shot", "toa"):
+        assert np.array_equal(cat[f], ref["events"][f]), f
+    assert np.array_equal(np.concatenate(trigs), ref["trig"])
+
+
+# ------------------------------------------------------------------ stream
+@pytest.mark.parametrize("name,shots", [("c1", 1000), ("c2", 300), ("c3", 120), ("c5", 150)])
+def test_stream_whole(tpx, orc, name, shots):
+    _say(f"stream whole {name} shots={shots}")
+    w = synth.make_config(name, n_shots=shots)
+    kw = dict(pix_epoch0=w.pix_epoch0, tdc_epoch0=w.tdc_epoch0)
+    ref, rst = orc.run(w.packets, **kw)
+    h, st = tpx.process_stream(w.packets, **kw)
+    assert_hits_match(h, ref)
+    for f in ("n_pixels", "n_tdc", "n_other", "n_pre_trigger", "n_tof_cut", "n_events"):
+        assert st[f] == rst[f], f
+    assert st["n_hits"] == ref.size and st["n_late_drop"] == 0
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_stream_chunked(tpx, orc, seed):
+    w = synth.make_config("c5", n_shots=120)
+    kw = dict(pix_epoch0=w.pix_epoch0, tdc_epoch0=w.tdc_epoch0)
+    ref, _ = orc.run(w.packets, **kw)
+    rng = np.random.default_rng(seed)
+    k = int(rng.integers(2, 40))
+    cuts = np.sort(rng.choice(np.arange(1, w.n_packets), k, replace=False))
+    parts = np.split(w.packets, cuts)
+    s = tpx.Stream(max(len(p) for p in parts), **kw)
+    out = []
+    for i, part in enumerate(parts):
+        h, st = s.process(part, flush=(i == len(parts) - 1))
+        out.append(h)
+        assert st["n_late_drop"] == 0
+    h = np.concatenate(out)
+    assert_hits_match(h, ref)
+    assert s.fallback_count == 0
+
+
+def test_stream_out_of_order_takes_general_path(tpx, orc):
+    """A kept pixel of one shot reported after pixels of the next shot: the
+    events are not in shot order and the general sorting path must give the
+    oracle's result."""
+    w = synth.make_config("c1", n_shots=60)
+    pk = w.packets.copy()
+    kept = np.nonzero(w.kept_mask())[0]
+    i = kept[np.argmax(w.shot[kept] == 10)]          # first kept pixel of shot 10
+    j = kept[np.argmax(w.shot[kept] == 12)]          # after trigger 12 in the stream
+    moved = np.concatenate([pk[:i], pk[i + 1:j + 1], pk[i:i + 1], pk[j + 1:]])
+    kw = dict(pix_epoch0=w.pix_epoch0, tdc_epoch0=w.tdc_epoch0)
+    ref, _ = orc.run(moved, **kw)
+    s = tpx.Stream(moved.size, **kw)
+    h, _ = s.process(moved, flush=True)
+    assert s.fallback_count == 1
+    assert_hits_match(h, ref)
+
+
+def test_stream_resume_from_checkpoint(tpx, orc):
+    w = synth.make_config("c5", n_shots=80)
+    kw = dict(pix_epoch0=w.pix_epoch0, tdc_epoch0=w.tdc_epoch0)
+    ref, _ = orc.run(w.packets, **kw)
+    half = w.n_packets // 2
+    a = tpx.Stream(w.n_packets, **kw)
+    h1, _ = a.process(w.packets[:half])
+    blob = a.get_state()
+    a.close()
+    b = tpx.Stream(w.n_packets, **kw)
+    b.set_state(blob)
+    h2, _ = b.process(w.packets[half:], flush=True)
+    assert_hits_match(np.concatenate([h1, h2]), ref)
+
+
+def test_deterministic(tpx):
+    w = synth.make_config("c2", n_shots=200)
+    kw = dict(pix_epoch0=w.pix_epoch0, tdc_epoch0=w.tdc_epoch0)
+    outs = [tpx.process_stream(w.packets, **kw)[0].tobytes() for _ in range(5)]
+    assert all(o == outs[0] for o in outs)
+
+
+# ---------------------------------------------------------------- centroid
+def test_centroid_given_labels(tpx, orc):
+    w = synth.make_config("c1", n_shots=500)
+    r = orc.process(w.packets, pix_epoch0=w.pix_epoch0, tdc_epoch0=w.tdc_epoch0)
+    e = r["events"]
+    d = tpx.to_device_events(e)
+    import torch
+    lab = torch.from_numpy(r["labels"].astype(np.uint32).view(np.int32)).cuda()
+    h = tpx.centroid(d, lab, r["trig"])
+    assert_hits_match(h, r["hits"])
+    # the same with events out of shot order
+    rng = np.random.default_rng(3)
+    perm = rng.permutation(e["x"].size)
+    inv = np.argsort(perm)
+    ep = {k: v[perm] for k, v in e.items()}
+    lp = inv[r["labels"][perm].astype(np.int64)]
+    # relabel so that every label is the smallest member index after the permutation
+    mins = {}
+    for i, l in enumerate(lp.tolist()):
+        mins[l] = min(mins.get(l, i), i)
+    lp2 = np.array([mins[l] for l in lp.tolist()], np.uint32)
+    href = orc.centroid(ep["x"], ep["y"], ep["tot"], ep["shot"], ep["toa"], lp2.astype(np.uint64),
+                        r["trig"])
+    h2 = tpx.centroid(tpx.to_device_events(ep), torch.from_numpy(lp2.view(np.int32)).cuda(),
+                      r["trig"])
+    assert_hits_match(h2, href)
+
+
+def test_walk_table(tpx, orc):
+    import torch
+    w = synth.make_config("c1", n_shots=300)
+    tot = np.arange(1024)
+    walk32 = (180.0 / (tot + 9.0) - 0.4).astype(np.float32)
+    kw = dict(pix_epoch0=w.pix_epoch0, tdc_epoch0=w.tdc_epoch0)
+    ref, _ = orc.run(w.packets, walk_ns=walk32.astype(np.float64), **kw)
+    lut = torch.from_numpy(walk32).cuda()
+    h, _ = tpx.process_stream(w.packets, walk_lut_ns=lut, **kw)
+    assert_hits_match(h, ref)
+
+
+# ---------------------------------------------------------------- ABI errors
+def test_abi_errors(tpx):
+    import torch
+    w = synth.make_config("c1", n_shots=50)
+    s = tpx.Stream(w.n_packets)
+    with pytest.raises(tpx.TpxError) as e:
+        s.process(w.packets, flush=True, hit_cap=10)
+    assert e.value.rc == tpx.ECAPACITY
+    h, _ = s.process(w.packets, flush=True)          # state unchanged: retry works
+    assert h.size > 10
+    # triggers going back in time
+    bad = synth.encode_tdc(np.array([5000, 1000]), np.array([0, 1]))
+    s2 = tpx.Stream(16)
+    with pytest.raises(tpx.TpxError) as e:
+        s2.process(bad, flush=True)
+    assert e.value.rc == tpx.ESTREAM
+    with pytest.raises(tpx.TpxError) as e:
+        s2.process(np.zeros(17, np.uint64))
+    assert e.value.rc == tpx.EINVAL
+    ev = tpx.to_device_events(dict(x=np.array([300], np.uint16), y=np.array([0], np.uint16),
+                                   tot=np.array([1], np.uint16), shot=np.array([0], np.uint32),
+                                   toa=np.array([0], np.uint64)))
+    with pytest.raises(tpx.TpxError) as e:
+        tpx.cluster(ev)
+    assert e.value.rc == tpx.EINVAL
+    torch.cuda.synchronize()
