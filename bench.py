@@ -1,0 +1,224 @@
+#!/usr/bin/env python3
+"""Benchmark of the TimePix3 VMI hot path on one MI355X.
+
+One step = tpx_process_stream over the whole synthetic c2 workload (100,000
+laser shots at 1 kHz, Poisson(30) hits per shot, spot sigma U(0.6, 1.5) px,
+10 % close pairs, TPX3 packets with spidr/ToA rollover and trigger words)
+with flush: decode, unwrap, shot assignment with the ToF cut, clustering and
+centroids of every hit.  The packets are resident in HBM before timing; each
+step starts from a fresh stream state.
+
+Prints one JSON line: pixel events/s (kept events that were clustered and
+centroided), the roofline of the dominant kernel (algorithmic bytes over its
+measured duration, HIP events on the stream it runs on), the oracle's
+throughput on a bounded sample on the host CPU, and p50/p99 chunk latency of a
+chunked c5 replay.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+HIT_BYTES = 48
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def stage_bytes(n_packets, n_events, n_hits):
+    """Algorithmic bytes each stage must move (inputs read once, outputs
+    written once)."""
+    return {
+        "tile_summary": 8 * n_packets,
+        "tile_prefix": 0,
+        "assign": 8 * n_packets + 8 * n_events,
+        "group": 0,
+        "cluster": 8 * n_events + HIT_BYTES * n_hits,
+        "carry": 0,
+    }
+
+
+def run_gpu(args, wl):
+    import torch
+
+    import paper_2603_04942_amd as tpx
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    pk = torch.from_numpy(wl.packets.view(np.int64)).to(dev)
+    n = pk.numel()
+    kw = dict(pix_epoch0=wl.pix_epoch0, tdc_epoch0=wl.tdc_epoch0)
+    s = tpx.Stream(n, **kw)
+    fresh = s.get_state()
+    cap = n // 4 + 1024
+    hits = torch.empty((cap, 48), dtype=torch.uint8, device=dev)
+    s.set_timing(True)
+
+    def step():
+        s.set_state(fresh)
+        rc, nh, st = s.process_raw(pk, True, hits, cap)
+        if rc != 0:
+            raise tpx.TpxError(rc, "tpx_process_stream", s.lib.tpx_last_error().decode())
+        return nh, st
+
+    for _ in range(args.warmup):
+        nh, st = step()
+    torch.cuda.synchronize()
+    stages = {}
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        nh, st = step()
+        for k, v in s.stage_times_ms().items():
+            stages[k] = stages.get(k, 0.0) + v
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1e3 / args.steps
+    stages = {k: v / args.steps for k, v in stages.items()}
+    stats = st.as_dict()
+    stats["n_hits"] = nh
+    s.close()
+    return ms, stages, stats
+
+
+def run_latency(args):
+    """Chunked replay of the c5 stream: per-chunk latency (call to results)."""
+    import torch
+
+    import paper_2603_04942_amd as tpx
+    import synth
+
+    w = synth.make_config("c5", n_shots=args.latency_shots, with_truth=False,
+                          workers=args.workers)
+    chunk = args.latency_chunk
+    pk = torch.from_numpy(w.packets.view(np.int64)).cuda()
+    s = tpx.Stream(chunk, pix_epoch0=w.pix_epoch0, tdc_epoch0=w.tdc_epoch0)
+    cap = chunk
+    hits = torch.empty((cap, 48), dtype=torch.uint8, device="cuda")
+    lat = []
+    n_ev = 0
+    starts = list(range(0, pk.numel(), chunk))
+    for i, a in enumerate(starts):
+        part = pk[a:a + chunk]
+        t = time.perf_counter()
+        rc, nh, st = s.process_raw(part, i == len(starts) - 1, hits, cap)
+        lat.append((time.perf_counter() - t) * 1e3)
+        if rc != 0:
+            raise tpx.TpxError(rc, "tpx_process_stream", s.lib.tpx_last_error().decode())
+        n_ev += st.n_events
+    s.close()
+    lat = np.array(lat[2:] if len(lat) > 4 else lat)
+    return dict(workload=f"c5: 1 kHz, Poisson(100) hits/shot, sigma 0.8 px, {args.latency_shots} "
+                         f"shots with a pixel-counter wrap, {chunk * 8 // 1024} KiB chunks",
+                chunks=int(len(starts)), p50_ms=float(np.percentile(lat, 50)),
+                p99_ms=float(np.percentile(lat, 99)), events=int(n_ev))
+
+
+def run_cpu_baseline(wl, frac):
+    import oracle
+
+    n = int(wl.n_packets * frac)
+    sample = np.ascontiguousarray(wl.packets[:n])
+    o = oracle.get()
+    t = time.perf_counter()
+    hits, st = o.run(sample, pix_epoch0=wl.pix_epoch0, tdc_epoch0=wl.tdc_epoch0)
+    dt = time.perf_counter() - t
+    return dict(value=st["n_events"] / dt, unit="events/s", cores=1, kind="oracle",
+                sample=f"first {n} packets ({frac:.0%}) of the c2 stream, {st['n_events']} "
+                       f"events, single-threaded C oracle, {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--shots", type=int, default=100_000, help="c2 shots (default: full size)")
+    ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
+    ap.add_argument("--cpu-frac", type=float, default=1.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-latency", action="store_true")
+    ap.add_argument("--latency-shots", type=int, default=3000)
+    ap.add_argument("--latency-chunk", type=int, default=131072, help="packets per chunk")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(each GPU would process its own range of shots; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import synth
+
+    t = time.perf_counter()
+    wl = synth.make_config("c2", n_shots=args.shots, with_truth=False, workers=args.workers)
+    log(f"generated c2: {wl.n_packets} packets in {time.perf_counter() - t:.1f} s")
+    ms, stages, stats = run_gpu(args, wl)
+    log(f"gpu: {ms:.3f} ms/step, stages {json.dumps({k: round(v, 4) for k, v in stages.items()})}")
+    n_ev, n_hits, n_pk = stats["n_events"], stats["n_hits"], wl.n_packets
+    value = n_ev / (ms * 1e-3)
+    sb = stage_bytes(n_pk, n_ev, n_hits)
+    dom = max(stages, key=stages.get)
+    achieved = sb[dom] / (stages[dom] * 1e-3) / 1e9
+    path_bytes = 8 * n_pk + HIT_BYTES * n_hits
+    out = {
+        "metric": "pixel events/s decoded+clustered+centroided at 1 GPU; % HBM peak; p99 chunk ms",
+        "value": value,
+        "unit": "events/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64",
+        "data": "synthetic",
+        "config": {
+            "workload": "c2: 100,000 shots at 1 kHz, Poisson(30) hits/shot, sigma U(0.6,1.5) px, "
+                        "10% close pairs, 1% dark counts, TPX3 packets with spidr/ToA rollover "
+                        "and trigger words; 8-connected, |dToA| <= 200 ns",
+            "shots": args.shots,
+            "packets": int(n_pk),
+            "events": int(n_ev),
+            "hits": int(n_hits),
+            "pixels_per_hit": n_ev / max(n_hits, 1),
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": dom,
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+        },
+        "path_roofline": {
+            "algorithmic_bytes_per_step": int(path_bytes),
+            "achieved": path_bytes / (ms * 1e-3) / 1e9,
+            "frac": path_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "unit": "GB/s",
+        },
+        "stages_ms": stages,
+        "hits_per_s": n_hits / (ms * 1e-3),
+        "acquisition_multiple": value / (n_ev / (args.shots * 1e-3)),
+    }
+    if not args.no_latency:
+        out["stream_latency"] = run_latency(args)
+        log(f"latency: {out['stream_latency']}")
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = run_cpu_baseline(wl, args.cpu_frac)
+        log(f"cpu baseline: {out['cpu_baseline']}")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -66,7 +66,8 @@ assert HIT_DTYPE.itemsize == 48
 EXPORTS = ("tpx_params_default", "tpx_unwrap_state_init", "tpx_workspace_bytes", "tpx_decode",
            "tpx_cluster", "tpx_centroid", "tpx_stream_create", "tpx_process_stream",
            "tpx_stream_get_state", "tpx_stream_set_state", "tpx_stream_destroy",
-           "tpx_status_str", "tpx_last_error", "tpx_stream_fallback_count")
+           "tpx_status_str", "tpx_last_error", "tpx_stream_fallback_count",
+           "tpx_stream_set_timing", "tpx_stream_get_timing", "tpx_stream_stage_name")
 
 _lib = None
 
@@ -101,6 +102,12 @@ def load(path=LIB_PATH):
     lib.tpx_last_error.restype = ctypes.c_char_p
     lib.tpx_stream_fallback_count.argtypes = [P]
     lib.tpx_stream_fallback_count.restype = ctypes.c_uint64
+    lib.tpx_stream_set_timing.argtypes = [P, ctypes.c_int]
+    lib.tpx_stream_set_timing.restype = I
+    lib.tpx_stream_get_timing.argtypes = [P, P, S, P]
+    lib.tpx_stream_get_timing.restype = I
+    lib.tpx_stream_stage_name.argtypes = [S]
+    lib.tpx_stream_stage_name.restype = ctypes.c_char_p
     for f in ("tpx_decode", "tpx_cluster", "tpx_centroid", "tpx_stream_create",
               "tpx_process_stream", "tpx_stream_get_state", "tpx_stream_set_state"):
         getattr(lib, f).restype = I
@@ -306,6 +313,16 @@ class Stream:
     def set_state(self, blob):
         buf = ctypes.create_string_buffer(blob, len(blob))
         _check(self.lib.tpx_stream_set_state(self.h, buf, len(blob)), "set_state")
+
+    def set_timing(self, enable=True):
+        _check(self.lib.tpx_stream_set_timing(self.h, int(enable)), "set_timing")
+
+    def stage_times_ms(self):
+        """{stage: ms} of the last process call (timing must be enabled)."""
+        buf = (ctypes.c_float * 8)()
+        n = ctypes.c_size_t()
+        _check(self.lib.tpx_stream_get_timing(self.h, buf, 8, ctypes.byref(n)), "get_timing")
+        return {self.lib.tpx_stream_stage_name(i).decode(): float(buf[i]) for i in range(n.value)}
 
     @property
     def fallback_count(self):

@@ -441,6 +441,10 @@ struct tpx_stream {
     uint64_t carry_last1;   // window index of the last carried event + 1 (0 = none)
     int cur;
     uint64_t n_fallback;    // chunks that needed the general (sorting) path
+    // optional per-stage timing with HIP events on the caller's stream
+    int timing;
+    hipEvent_t tev[8];
+    float stage_ms[7];
 };
 
 namespace {
@@ -459,6 +463,8 @@ tpx_status dalloc(tpx_stream* s, T** p, uint64_t count) {
 }
 
 void free_stream(tpx_stream* s) {
+    if (s->timing)
+        for (auto& e : s->tev) (void)hipEventDestroy(e);
     for (void* q : s->allocs) (void)hipFree(q);
     if (s->res_h) (void)hipHostFree(s->res_h);
     delete s;
@@ -511,13 +517,25 @@ AssignArgs stream_assign_args(tpx_stream* s, const uint64_t* chunk, uint64_t n) 
     return a;
 }
 
-// decode + assign of one chunk (shared by both paths)
+void mark(tpx_stream* s, int i, hipStream_t hs) {
+    if (s->timing) (void)hipEventRecord(s->tev[i], hs);
+}
+
+// decode front end of one chunk (shared by both paths)
 void stream_front(tpx_stream* s, const uint64_t* chunk, uint64_t n, hipStream_t hs) {
     zero_res(s->res, hs);
-    launch_front(chunk, n, s->p, s->dw, run_of(s->pix_has, s->pix_last),
-                 run_of(s->tdc_has, s->tdc_last), s->pix_epoch, s->tdc_epoch, s->tab[s->cur],
-                 s->n_win, hs);
-    launch_fill_u64(s->lb_seg, 0, s->seg_cap, hs);
+    mark(s, 0, hs);
+    const uint64_t nt = ntiles_of(n);
+    launch_tile_summary(chunk, n, s->p.trig_subtype, s->p.jump_ticks, s->dw.sums, s->dw.tdc_slot,
+                        s->dw.tdc_cnt, hs);
+    mark(s, 1, hs);
+    launch_tile_scan(s->dw.sums, s->dw.tdc_cnt, nt, run_of(s->pix_has, s->pix_last),
+                     run_of(s->tdc_has, s->tdc_last), s->pix_epoch, s->tdc_epoch,
+                     s->p.jump_ticks, s->dw.entries, s->res, hs);
+    launch_trig_unwrap(s->dw.entries, s->dw.tdc_cnt, s->dw.tdc_slot, nt, s->p.jump_ticks,
+                       s->tab[s->cur] + s->n_win, s->res, hs);
+    launch_fill_u64(s->dw.lb, 0, nt + 1, hs);
+    launch_fill_u64(s->lb_seg, 0, (s->n_carry + n) / kQ + 4, hs);
 }
 
 tpx_status stream_fast(tpx_stream* s, const uint64_t* chunk, uint64_t n, int flush, tpx_hit* hits,
@@ -529,7 +547,9 @@ tpx_status stream_fast(tpx_stream* s, const uint64_t* chunk, uint64_t n, int flu
                     s->shot_cnt, hs);
     AssignArgs a = stream_assign_args(s, chunk, n);
     a.shot_cnt = s->shot_cnt;
+    mark(s, 2, hs);
     launch_assign(a, false, hs);
+    mark(s, 3, hs);
     launch_tiles_sorted(s->dw.recs, ntiles_of(n), s->carry_last1, s->res, hs);
     launch_set_rows(s->res, s->n_win, hs);
     launch_scan_u32(s->shot_cnt, s->shot_off, 0, &s->res->n_groups, s->block_tmp, hs);
@@ -541,12 +561,18 @@ tpx_status stream_fast(tpx_stream* s, const uint64_t* chunk, uint64_t n, int flu
     c.n_ev_dev = &s->res->n_close_ev;
     c.n_grp_dev = &s->res->n_close_grp;
     c.skip = &s->res->unsorted;
-    launch_cluster(c, false, cluster_grid(s->ev_cap, kQ), hs);
+    mark(s, 4, hs);
+    launch_cluster(c, false, cluster_grid(s->n_carry + n, kQ), hs);
+    mark(s, 5, hs);
     const int nx = 1 - s->cur;
     launch_carry_out(s->ev, nullptr, nullptr, s->shot_off, &s->res->n_groups, &s->res->n_close_ev,
                      &s->res->n_kept, s->c_gidx[s->cur], s->n_carry, s->ev_next, s->c_ev[nx],
                      s->c_shot[nx], s->c_gidx[nx], s->carry_cap, s->res, hs);
-    return read_res(s->res, s->res_h, hs);
+    mark(s, 6, hs);
+    tpx_status rc = read_res(s->res, s->res_h, hs);
+    if (rc == TPX_OK && s->timing)
+        for (int i = 0; i < 6; ++i) (void)hipEventElapsedTime(&s->stage_ms[i], s->tev[i], s->tev[i + 1]);
+    return rc;
 }
 
 // Events not in shot order: materialise every event's shot, sort stably by
@@ -579,7 +605,7 @@ tpx_status stream_general(tpx_stream* s, const uint64_t* chunk, uint64_t n, int 
     c.grp_shot = s->grp_shot;
     c.n_ev_dev = &s->res->n_close_ev;
     c.n_grp_dev = &s->res->n_close_list;
-    launch_cluster(c, false, cluster_grid(s->ev_cap, kQ), hs);
+    launch_cluster(c, false, cluster_grid(N, kQ), hs);
     const int nx = 1 - s->cur;
     launch_carry_out(s->ev_sorted, vo, ko, nullptr, nullptr, &s->res->n_close_ev, &s->res->n_kept,
                      s->c_gidx[s->cur], s->n_carry, s->ev_next, s->c_ev[nx], s->c_shot[nx],
@@ -818,5 +844,30 @@ tpx_status tpx_stream_set_state(tpx_stream* s, const void* buf_h, size_t bytes) 
 
 // Diagnostics for tests and benchmarks: chunks that took the general path.
 uint64_t tpx_stream_fallback_count(const tpx_stream* s) { return s ? s->n_fallback : 0; }
+
+static const char* const kStageNames[6] = {"tile_summary", "tile_prefix", "assign",
+                                           "group",        "cluster",     "carry"};
+
+tpx_status tpx_stream_set_timing(tpx_stream* s, int enable) {
+    if (!s) return fail(TPX_EINVAL, "stream is NULL");
+    if (enable && !s->timing) {
+        for (auto& e : s->tev) HIPCHK(hipEventCreate(&e));
+        s->timing = 1;
+    } else if (!enable && s->timing) {
+        for (auto& e : s->tev) (void)hipEventDestroy(e);
+        s->timing = 0;
+    }
+    return TPX_OK;
+}
+
+tpx_status tpx_stream_get_timing(const tpx_stream* s, float* ms_h, size_t n, size_t* n_stages_h) {
+    if (!s || !n_stages_h) return fail(TPX_EINVAL, "NULL argument");
+    *n_stages_h = 6;
+    if (!s->timing) return fail(TPX_EINVAL, "timing is not enabled");
+    for (size_t i = 0; i < n && i < 6; ++i) ms_h[i] = s->stage_ms[i];
+    return TPX_OK;
+}
+
+const char* tpx_stream_stage_name(size_t i) { return i < 6 ? kStageNames[i] : ""; }
 
 }  // extern "C"
