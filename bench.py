@@ -71,6 +71,16 @@ def run_gpu(args, wl):
             raise tpx.TpxError(rc, "tpx_process_stream", s.lib.tpx_last_error().decode())
         return nh, st
 
+    if args.copy_calib_mb:
+        # a plain device copy of known size: its FETCH_SIZE / WRITE_SIZE
+        # counters calibrate the HBM traffic counters of the kernels above
+        nb = args.copy_calib_mb << 20
+        src = torch.ones(nb // 8, dtype=torch.int64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         nh, st = step()
     torch.cuda.synchronize()
@@ -91,7 +101,11 @@ def run_gpu(args, wl):
 
 
 def run_latency(args):
-    """Chunked replay of the c5 stream: per-chunk latency (call to results)."""
+    """Chunked replay of the c5 stream (1 kHz, Poisson(100) hits per shot, a
+    pixel-counter wrap inside).  For each chunk size: back-to-back chunks
+    (saturated: latency = processing time of one chunk), and paced replays in
+    which chunk k is released when its last word would have been acquired at
+    speedup x; latency = completion - release."""
     import torch
 
     import paper_2603_04942_amd as tpx
@@ -99,28 +113,53 @@ def run_latency(args):
 
     w = synth.make_config("c5", n_shots=args.latency_shots, with_truth=False,
                           workers=args.workers)
-    chunk = args.latency_chunk
     pk = torch.from_numpy(w.packets.view(np.int64)).cuda()
-    s = tpx.Stream(chunk, pix_epoch0=w.pix_epoch0, tdc_epoch0=w.tdc_epoch0)
-    cap = chunk
-    hits = torch.empty((cap, 48), dtype=torch.uint8, device="cuda")
-    lat = []
-    n_ev = 0
-    starts = list(range(0, pk.numel(), chunk))
-    for i, a in enumerate(starts):
-        part = pk[a:a + chunk]
-        t = time.perf_counter()
-        rc, nh, st = s.process_raw(part, i == len(starts) - 1, hits, cap)
-        lat.append((time.perf_counter() - t) * 1e3)
-        if rc != 0:
-            raise tpx.TpxError(rc, "tpx_process_stream", s.lib.tpx_last_error().decode())
-        n_ev += st.n_events
-    s.close()
-    lat = np.array(lat[2:] if len(lat) > 4 else lat)
-    return dict(workload=f"c5: 1 kHz, Poisson(100) hits/shot, sigma 0.8 px, {args.latency_shots} "
-                         f"shots with a pixel-counter wrap, {chunk * 8 // 1024} KiB chunks",
-                chunks=int(len(starts)), p50_ms=float(np.percentile(lat, 50)),
-                p99_ms=float(np.percentile(lat, 99)), events=int(n_ev))
+    n_pk = pk.numel()
+    acq_s = args.latency_shots * 1e-3          # 1 kHz
+    pk_rate = n_pk / acq_s                     # packets per second of acquisition
+    out = dict(workload=f"c5: 1 kHz, Poisson(100) hits/shot, sigma 0.8 px, {args.latency_shots} "
+                        f"shots, {n_pk} packets, a pixel-counter wrap inside",
+               sizes=[])
+    for chunk in args.latency_chunks:
+        s = tpx.Stream(chunk, pix_epoch0=w.pix_epoch0, tdc_epoch0=w.tdc_epoch0)
+        hits = torch.empty((chunk, 48), dtype=torch.uint8, device="cuda")
+        starts = list(range(0, n_pk, chunk))
+
+        def replay(limit, speed):
+            s.set_state(fresh)
+            lat, n_ev = [], 0
+            t0 = time.perf_counter()
+            for i, a in enumerate(starts[:limit]):
+                last = i == len(starts) - 1 or i == limit - 1
+                rel = t0 + (min(a + chunk, n_pk) / pk_rate / speed if speed else 0.0)
+                if speed:
+                    while time.perf_counter() < rel:
+                        pass
+                else:
+                    rel = time.perf_counter()
+                rc, nh, st = s.process_raw(pk[a:a + chunk], last, hits, chunk)
+                lat.append((time.perf_counter() - rel) * 1e3)
+                if rc != 0:
+                    raise tpx.TpxError(rc, "tpx_process_stream", s.lib.tpx_last_error().decode())
+                n_ev += st.n_events
+            return np.array(lat), n_ev, time.perf_counter() - t0
+
+        fresh = s.get_state()
+        replay(min(len(starts), 8), 0)           # warm-up
+        lat, n_ev, span = replay(len(starts), 0)
+        row = dict(chunk_packets=chunk, chunk_kib=chunk * 8 // 1024, chunks=len(starts),
+                   p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
+                   events_per_s=n_ev / span, replay_capacity=acq_s / span, paced={})
+        for speed in args.latency_speeds:
+            # bound each paced run to about 2 s of wall time
+            lim = max(1, min(len(starts), int(2.0 * pk_rate * speed / chunk)))
+            lat_p, _, _ = replay(lim, speed)
+            row["paced"][f"{speed:g}x"] = dict(chunks=lim, p50_ms=float(np.percentile(lat_p, 50)),
+                                               p99_ms=float(np.percentile(lat_p, 99)))
+        out["sizes"].append(row)
+        s.close()
+        del hits
+    return out
 
 
 def run_cpu_baseline(wl, frac):
@@ -147,8 +186,14 @@ def main():
     ap.add_argument("--cpu-frac", type=float, default=1.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-latency", action="store_true")
-    ap.add_argument("--latency-shots", type=int, default=3000)
-    ap.add_argument("--latency-chunk", type=int, default=131072, help="packets per chunk")
+    ap.add_argument("--latency-shots", type=int, default=36000)
+    ap.add_argument("--latency-chunks", type=int, nargs="+", default=[8192, 131072, 2097152],
+                    help="packets per chunk (64 KiB, 1 MiB, 16 MiB)")
+    ap.add_argument("--latency-speeds", type=float, nargs="+", default=[1.0, 10.0, 200.0],
+                    help="paced replay speedups over acquisition")
+    ap.add_argument("--copy-calib-mb", type=int, default=0,
+                    help="run one plain device copy of this many MiB before timing "
+                         "(calibration of HBM traffic counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

@@ -33,6 +33,9 @@ tpx_status fail(tpx_status st, const char* fmt, ...) {
 
 constexpr uint32_t kQ = 1024;           // segment stride (events)
 constexpr uint64_t kMaxEvents = 0xFFFFFFF0ull;
+// packets in one decode call: the tile look-back keeps a kept-event count and a
+// trigger-table index in 31 bits each
+constexpr uint64_t kMaxCallPkts = (1ull << 31) - 16;
 
 uint64_t ntiles_of(uint64_t n) { return (n + kTilePkts - 1) / kTilePkts; }
 
@@ -65,31 +68,32 @@ struct Carve {
 
 struct DecodeWs {
     DevResults* res;
-    TileSum* sums;
+    TileAcc* sums;
+    TileAcc* partial;
+    TileAcc* blk;
     TileEntry* entries;
-    uint32_t* tdc_cnt;
     uint64_t* tdc_slot;
     uint64_t* tab;
     uint64_t* lb;
-    TileRec* recs;
 };
 DecodeWs carve_decode(Carve& c, uint64_t n) {
     const uint64_t nt = ntiles_of(n) + 1;
     DecodeWs w;
     w.res = c.take<DevResults>(1);
-    w.sums = c.take<TileSum>(nt);
+    w.sums = c.take<TileAcc>(nt);
+    w.partial = c.take<TileAcc>(nt);
+    w.blk = c.take<TileAcc>(2 * tile_scan_blocks(nt) + 2);
     w.entries = c.take<TileEntry>(nt);
-    w.tdc_cnt = c.take<uint32_t>(nt);
     w.tdc_slot = c.take<uint64_t>(nt * kTilePkts);
     w.tab = c.take<uint64_t>(n + 2);
     w.lb = c.take<uint64_t>(nt);
-    w.recs = c.take<TileRec>(nt);
     return w;
 }
 
 struct ClusterWs {
     DevResults* res;
     uint32_t *flags, *scan, *block_tmp, *keys, *vals, *keys2, *vals2, *grp_off, *grp_shot;
+    uint32_t* seg_lo;
     uint64_t* lb;
     uint32_t* big[6];
     uint64_t* acc;
@@ -106,6 +110,7 @@ ClusterWs carve_cluster(Carve& c, uint64_t m, bool with_acc) {
     w.vals2 = c.take<uint32_t>(m + 1);
     w.grp_off = c.take<uint32_t>(m + 2);
     w.grp_shot = c.take<uint32_t>(m + 1);
+    w.seg_lo = c.take<uint32_t>(m / kQ + 4);
     w.lb = c.take<uint64_t>(m / kQ + 4);
     for (int k = 0; k < 6; ++k) w.big[k] = c.take<uint32_t>(m + 1);
     w.acc = with_acc ? c.take<uint64_t>(10 * (m + 1)) : nullptr;
@@ -171,9 +176,11 @@ void launch_front(const uint64_t* pk, uint64_t n, const tpx_params& p, const Dec
                   RunSum pix0, RunSum tdc0, int64_t pe0, int64_t te0, uint64_t* tab,
                   uint64_t n_win, hipStream_t s) {
     const uint64_t nt = ntiles_of(n);
-    launch_tile_summary(pk, n, p.trig_subtype, p.jump_ticks, w.sums, w.tdc_slot, w.tdc_cnt, s);
-    launch_tile_scan(w.sums, w.tdc_cnt, nt, pix0, tdc0, pe0, te0, p.jump_ticks, w.entries, w.res, s);
-    launch_trig_unwrap(w.entries, w.tdc_cnt, w.tdc_slot, nt, p.jump_ticks, tab + n_win, w.res, s);
+    launch_tile_summary(pk, n, p.trig_subtype, p.jump_ticks, w.sums, w.tdc_slot, s);
+    launch_tile_scan(w.sums, nt, TileAcc{pix0, tdc0, 0}, pe0, te0, p.jump_ticks, w.partial, w.blk,
+                     w.res, s);
+    launch_trig_unwrap(w.sums, w.partial, w.blk, w.tdc_slot, nt, pe0, te0, p.jump_ticks,
+                       w.entries, tab + n_win, w.res, s);
     launch_fill_u64(w.lb, 0, nt + 1, s);
 }
 
@@ -239,7 +246,7 @@ tpx_status tpx_decode(const uint64_t* pkts, size_t n_pkts, const tpx_params* p_h
     if (ev_cap && (!ev.x || !ev.y || !ev.tot || !ev.shot || !ev.toa))
         return fail(TPX_EINVAL, "an event array is NULL");
     if (trig_cap && !trig_toa) return fail(TPX_EINVAL, "trig_toa is NULL");
-    if (n_pkts >= kMaxEvents) return fail(TPX_EINVAL, "too many packets in one call");
+    if (n_pkts >= kMaxCallPkts) return fail(TPX_EINVAL, "too many packets in one call");
     if (!ws || ws_bytes < tpx_workspace_bytes(n_pkts, 0))
         return fail(TPX_EINVAL, "workspace too small (need %zu bytes)", tpx_workspace_bytes(n_pkts, 0));
     if (st_h->pix_epoch < 0 || st_h->tdc_epoch < 0) return fail(TPX_EINVAL, "negative epoch in state");
@@ -259,6 +266,7 @@ tpx_status tpx_decode(const uint64_t* pkts, size_t n_pkts, const tpx_params* p_h
     a.tof_max = p_h->tof_max_ticks;
     a.jump = p_h->jump_ticks;
     a.entries = w.entries;
+    a.sums = w.sums;
     a.tab = w.tab;
     a.n_win = n_win;
     a.n_trig_dev = &w.res->n_trig;
@@ -267,7 +275,6 @@ tpx_status tpx_decode(const uint64_t* pkts, size_t n_pkts, const tpx_params* p_h
     a.ev_cap = ev_cap;
     a.soa = ev;
     a.shot_base = st_h->trig_base - n_win;
-    a.recs = w.recs;
     a.lb_status = w.lb;
     a.res = w.res;
     launch_assign(a, true, s);
@@ -338,6 +345,7 @@ tpx_status tpx_cluster(tpx_events ev, size_t n_ev, const tpx_params* p_h, uint32
     a.grp_shot = w.grp_shot;
     a.n_ev_dev = &w.res->n_in;
     a.n_grp_dev = &w.res->n_groups;
+    a.seg_lo = w.seg_lo;
     a.q = kQ;
     a.dxy = p_h->dxy;
     a.dt = p_h->dt_ticks;
@@ -350,6 +358,7 @@ tpx_status tpx_cluster(tpx_events ev, size_t n_ev, const tpx_params* p_h, uint32
     a.g_t = w.big[3];
     a.g_sl = w.big[4];
     a.g_xy = w.big[5];
+    launch_seg_table(w.grp_off, a.n_grp_dev, a.n_ev_dev, nullptr, kQ, n_ev, w.seg_lo, s);
     launch_cluster(a, true, cluster_grid(n_ev, kQ), s);
     if ((rc = read_res(w.res, &r, s))) return rc;
     if ((rc = res_error(r))) return rc;
@@ -425,6 +434,7 @@ struct tpx_stream {
     uint64_t* ev_sorted;
     uint32_t* block_tmp;
     uint64_t* lb_seg;
+    uint32_t* seg_lo;
     uint32_t* big[6];
     uint64_t* g_acc;
     // committed host state
@@ -503,6 +513,7 @@ AssignArgs stream_assign_args(tpx_stream* s, const uint64_t* chunk, uint64_t n) 
     a.tof_max = s->p.tof_max_ticks;
     a.jump = s->p.jump_ticks;
     a.entries = s->dw.entries;
+    a.sums = s->dw.sums;
     a.tab = s->tab[s->cur];
     a.n_win = s->n_win;
     a.n_trig_dev = &s->res->n_trig;
@@ -511,7 +522,7 @@ AssignArgs stream_assign_args(tpx_stream* s, const uint64_t* chunk, uint64_t n) 
     a.ev = s->ev;
     a.ev_off = s->n_carry;
     a.ev_cap = s->ev_cap;
-    a.recs = s->dw.recs;
+    a.carry_last1 = s->carry_last1;
     a.lb_status = s->dw.lb;
     a.res = s->res;
     return a;
@@ -527,13 +538,15 @@ void stream_front(tpx_stream* s, const uint64_t* chunk, uint64_t n, hipStream_t 
     mark(s, 0, hs);
     const uint64_t nt = ntiles_of(n);
     launch_tile_summary(chunk, n, s->p.trig_subtype, s->p.jump_ticks, s->dw.sums, s->dw.tdc_slot,
-                        s->dw.tdc_cnt, hs);
+                        hs);
     mark(s, 1, hs);
-    launch_tile_scan(s->dw.sums, s->dw.tdc_cnt, nt, run_of(s->pix_has, s->pix_last),
-                     run_of(s->tdc_has, s->tdc_last), s->pix_epoch, s->tdc_epoch,
-                     s->p.jump_ticks, s->dw.entries, s->res, hs);
-    launch_trig_unwrap(s->dw.entries, s->dw.tdc_cnt, s->dw.tdc_slot, nt, s->p.jump_ticks,
-                       s->tab[s->cur] + s->n_win, s->res, hs);
+    launch_tile_scan(s->dw.sums, nt,
+                     TileAcc{run_of(s->pix_has, s->pix_last), run_of(s->tdc_has, s->tdc_last), 0},
+                     s->pix_epoch, s->tdc_epoch, s->p.jump_ticks, s->dw.partial, s->dw.blk, s->res,
+                     hs);
+    launch_trig_unwrap(s->dw.sums, s->dw.partial, s->dw.blk, s->dw.tdc_slot, nt, s->pix_epoch,
+                       s->tdc_epoch, s->p.jump_ticks, s->dw.entries, s->tab[s->cur] + s->n_win,
+                       s->res, hs);
     launch_fill_u64(s->dw.lb, 0, nt + 1, hs);
     launch_fill_u64(s->lb_seg, 0, (s->n_carry + n) / kQ + 4, hs);
 }
@@ -550,7 +563,6 @@ tpx_status stream_fast(tpx_stream* s, const uint64_t* chunk, uint64_t n, int flu
     mark(s, 2, hs);
     launch_assign(a, false, hs);
     mark(s, 3, hs);
-    launch_tiles_sorted(s->dw.recs, ntiles_of(n), s->carry_last1, s->res, hs);
     launch_set_rows(s->res, s->n_win, hs);
     launch_scan_u32(s->shot_cnt, s->shot_off, 0, &s->res->n_groups, s->block_tmp, hs);
     launch_close(s->tab[s->cur], &s->res->n_trig, s->n_win, s->first_open, flush, s->max_t_plus1,
@@ -561,6 +573,8 @@ tpx_status stream_fast(tpx_stream* s, const uint64_t* chunk, uint64_t n, int flu
     c.n_ev_dev = &s->res->n_close_ev;
     c.n_grp_dev = &s->res->n_close_grp;
     c.skip = &s->res->unsorted;
+    c.seg_lo = s->seg_lo;
+    launch_seg_table(c.grp_off, c.n_grp_dev, c.n_ev_dev, c.skip, kQ, rows, s->seg_lo, hs);
     mark(s, 4, hs);
     launch_cluster(c, false, cluster_grid(s->n_carry + n, kQ), hs);
     mark(s, 5, hs);
@@ -605,6 +619,8 @@ tpx_status stream_general(tpx_stream* s, const uint64_t* chunk, uint64_t n, int 
     c.grp_shot = s->grp_shot;
     c.n_ev_dev = &s->res->n_close_ev;
     c.n_grp_dev = &s->res->n_close_list;
+    c.seg_lo = s->seg_lo;
+    launch_seg_table(c.grp_off, c.n_grp_dev, c.n_ev_dev, nullptr, kQ, N, s->seg_lo, hs);
     launch_cluster(c, false, cluster_grid(N, kQ), hs);
     const int nx = 1 - s->cur;
     launch_carry_out(s->ev_sorted, vo, ko, nullptr, nullptr, &s->res->n_close_ev, &s->res->n_kept,
@@ -621,7 +637,7 @@ tpx_status tpx_stream_create(const tpx_params* p_h, size_t max_chunk_pkts, tpx_s
     tpx_status rc = check_params(p_h);
     if (rc) return rc;
     if (!out_h) return fail(TPX_EINVAL, "out_h is NULL");
-    if (max_chunk_pkts == 0 || max_chunk_pkts >= kMaxEvents / 2)
+    if (max_chunk_pkts == 0 || max_chunk_pkts >= kMaxCallPkts / 2)
         return fail(TPX_EINVAL, "max_chunk_pkts out of range");
     tpx_stream* s = new tpx_stream();  // value-initialised: every scalar starts at zero
     s->p = *p_h;
@@ -646,11 +662,11 @@ tpx_status tpx_stream_create(const tpx_params* p_h, size_t max_chunk_pkts, tpx_s
     ALLOC(s->res, 1);
     s->dw.res = s->res;
     ALLOC(s->dw.sums, nt);
+    ALLOC(s->dw.partial, nt);
+    ALLOC(s->dw.blk, 2 * tile_scan_blocks(nt) + 2);
     ALLOC(s->dw.entries, nt);
-    ALLOC(s->dw.tdc_cnt, nt);
     ALLOC(s->dw.tdc_slot, nt * kTilePkts);
     ALLOC(s->dw.lb, nt + 1);
-    ALLOC(s->dw.recs, nt);
     ALLOC(s->tab[0], s->tab_cap);
     ALLOC(s->tab[1], s->tab_cap);
     ALLOC(s->shot_cnt, s->tab_cap + 2);
@@ -673,6 +689,7 @@ tpx_status tpx_stream_create(const tpx_params* p_h, size_t max_chunk_pkts, tpx_s
     ALLOC(s->ev_sorted, s->ev_cap);
     ALLOC(s->block_tmp, 1024);
     ALLOC(s->lb_seg, s->seg_cap);
+    ALLOC(s->seg_lo, s->seg_cap);
     for (int k = 0; k < 6; ++k) ALLOC(s->big[k], s->ev_cap);
     ALLOC(s->g_acc, 6 * s->ev_cap);
 #undef ALLOC

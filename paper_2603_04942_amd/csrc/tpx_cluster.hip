@@ -199,18 +199,17 @@ __device__ inline void write_hit(const ClusterArgs& a, uint64_t h, uint32_t g, u
     a.hits[h] = o;
 }
 
-// look-back over segments; returns this segment's first output slot
+// Look-back over segments by the 64 lanes of wave 0; returns this segment's
+// first output slot.
 __device__ inline uint64_t seg_lookback(const ClusterArgs& a, uint64_t ticket, uint32_t count) {
-    if (ticket == 0) {
-        lb_publish(a.lb_status, 0, kLbInclusive, count);
-        return 0;
+    uint64_t p = 0;
+    if (ticket > 0) {
+        if (__lane_id() == 0) lb_publish(a.lb_status, ticket, kLbAggregate, count);
+        p = lb_lookback_wave<LbSum>(a.lb_status, ticket, &a.res->err);
     }
-    lb_publish(a.lb_status, ticket, kLbAggregate, count);
-    const uint64_t p = lb_lookback(a.lb_status, ticket, &a.res->err);
-    lb_publish(a.lb_status, ticket, kLbInclusive, p + count);
+    if (__lane_id() == 0) lb_publish(a.lb_status, ticket, kLbInclusive, p + count);
     return p;
 }
-
 
 // Visit every chained event of image slot (nx, ny) that is a neighbour of
 // event i (same shot, |dx|, |dy| <= r, |dt| <= dt) and unite with it.  On the
@@ -391,9 +390,12 @@ __device__ void seg_small(const ClusterArgs& a, uint8_t* lds, uint32_t* scan_tmp
             rank[k] = running + wg_flag_scan<kWG>(is_root, scan_tmp, &tot);
             running += tot;
         }
-        if (tid == 0) {
-            bc[1] = seg_lookback(a, ticket, running);
-            if (running) atomicAdd(&a.res->n_hits, (unsigned long long)running);
+        if (tid < 64) {
+            const uint64_t p = seg_lookback(a, ticket, running);
+            if (tid == 0) {
+                bc[1] = p;
+                if (running) atomicAdd(&a.res->n_hits, (unsigned long long)running);
+            }
         }
         __syncthreads();
         const uint64_t out0 = bc[1];
@@ -518,9 +520,12 @@ __device__ void seg_big(const ClusterArgs& a, uint8_t* lds, uint32_t* scan_tmp, 
             if (is_root) par[i] = rk;  // parents are no longer needed: keep the rank
             running += tot;
         }
-        if (tid == 0) {
-            bc[1] = seg_lookback(a, ticket, running);
-            if (running) atomicAdd(&a.res->n_hits, (unsigned long long)running);
+        if (tid < 64) {
+            const uint64_t p = seg_lookback(a, ticket, running);
+            if (tid == 0) {
+                bc[1] = p;
+                if (running) atomicAdd(&a.res->n_hits, (unsigned long long)running);
+            }
         }
         __syncthreads();
         const uint64_t out0 = bc[1];
@@ -534,6 +539,34 @@ __device__ void seg_big(const ClusterArgs& a, uint8_t* lds, uint32_t* scan_tmp, 
     }
 }
 
+// Segment table: seg_lo[k] = first group whose first event is at or after
+// k q, for k = 0..n_seg (n_seg = ceil(N / q)).  One thread per group g = 0..G
+// fills the k in (grp_off[g-1] / q, grp_off[g] / q]; g = G closes at n_seg.
+__global__ void k_seg_table(const uint32_t* __restrict__ grp_off, const unsigned long long* n_grp_dev,
+                            const unsigned long long* n_ev_dev, const unsigned long long* skip,
+                            uint32_t q, uint32_t* seg_lo) {
+    if (skip && *skip) return;
+    const uint64_t G = *n_grp_dev, N = *n_ev_dev;
+    const uint64_t n_seg = (N + q - 1) / q;
+    for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g <= G;
+         g += (uint64_t)gridDim.x * blockDim.x) {
+        // offsets never exceed N in a valid table; the clamps keep every
+        // write inside seg_lo[0..n_seg] whatever the table holds
+        const int64_t k_prev = g == 0 ? -1 : (int64_t)min<uint64_t>(grp_off[g - 1] / q, n_seg);
+        const int64_t k_hi = g == G ? (int64_t)n_seg : (int64_t)min<uint64_t>(grp_off[g] / q, n_seg);
+        for (int64_t k = k_prev + 1; k <= k_hi; ++k) seg_lo[k] = (uint32_t)g;
+    }
+}
+
+void launch_seg_table(const uint32_t* grp_off, const unsigned long long* n_grp_dev,
+                      const unsigned long long* n_ev_dev, const unsigned long long* skip,
+                      uint32_t q, uint64_t max_groups, uint32_t* seg_lo, hipStream_t s) {
+    uint64_t blocks = (max_groups + 1 + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_seg_table, dim3((unsigned)blocks), dim3(256), 0, s, grp_off, n_grp_dev,
+                       n_ev_dev, skip, q, seg_lo);
+}
+
 // One workgroup per segment.  The grid covers the largest possible number of
 // segments; workgroups whose ticket is beyond the actual count return at once.
 template <bool kEvent>
@@ -543,50 +576,27 @@ __global__ __launch_bounds__(kWG, 2) void k_cluster(ClusterArgs a) {
     __shared__ uint64_t bc[8];
     __shared__ uint32_t goff[kWG + 1];
     const int tid = threadIdx.x;
-    if (tid == 0) {
-        const uint64_t N = (a.skip && *a.skip) ? 0 : *a.n_ev_dev;
-        const uint64_t G = *a.n_grp_dev;
-        const uint64_t q = a.q;
-        const uint64_t n_seg = (N + q - 1) / q;
-        const uint64_t k = atomicAdd(&a.res->seg_ticket, 1ull);
-        uint64_t g_lo = 0, g_hi = 0, e0 = 0, e1 = 0;
-        if (k < n_seg) {
-            // groups whose first event lies in [k q, (k+1) q)
-            uint64_t lo = 0, hi = G;
-            const uint64_t v0 = k * q;
-            while (lo < hi) {
-                const uint64_t m = (lo + hi) >> 1;
-                if (a.grp_off[m] < v0) lo = m + 1; else hi = m;
-            }
-            g_lo = lo;
-            hi = G;
-            const uint64_t v1 = (k + 1) * q;
-            while (lo < hi) {
-                const uint64_t m = (lo + hi) >> 1;
-                if (a.grp_off[m] < v1) lo = m + 1; else hi = m;
-            }
-            g_hi = lo;
-            e0 = a.grp_off[g_lo];
-            e1 = a.grp_off[g_hi];
-        }
-        bc[0] = k;
-        bc[2] = g_lo;
-        bc[3] = g_hi;
-        bc[4] = e0;
-        bc[5] = e1;
-        bc[6] = k < n_seg ? 1 : 0;
-    }
+    if (tid == 0) bc[0] = atomicAdd(&a.res->seg_ticket, 1ull);
     __syncthreads();
-    const uint64_t k = bc[0];
-    const bool active = bc[6] != 0;
-    const uint32_t g_lo = (uint32_t)bc[2], g_hi = (uint32_t)bc[3];
-    const uint64_t e0 = bc[4];
-    const uint32_t n = (uint32_t)(bc[5] - bc[4]);
+    const uint32_t k = __builtin_amdgcn_readfirstlane((uint32_t)bc[0]);
+    const uint64_t N = (a.skip && *a.skip) ? 0 : *a.n_ev_dev;
+    const uint64_t n_seg = (N + a.q - 1) / a.q;
+    if (k >= n_seg) return;
+    // groups whose first event lies in [k q, (k+1) q)
+    const uint32_t g_lo = a.seg_lo[k], g_hi = a.seg_lo[k + 1];
+    const uint64_t e0 = a.grp_off[g_lo], e1 = a.grp_off[g_hi];
+    if (g_hi < g_lo || e1 < e0 || e1 > N) {
+        if (tid == 0) {
+            atomicOr(&a.res->err, (unsigned long long)kErrInternal);
+            if (!kEvent) lb_publish(a.lb_status, k, kLbAggregate, 0);
+        }
+        return;
+    }
+    const uint32_t n = (uint32_t)(e1 - e0);
     const uint32_t ng = g_hi - g_lo;
-    if (!active) return;
     if (n == 0) {
         if constexpr (!kEvent) {
-            if (tid == 0) seg_lookback(a, k, 0);
+            if (tid == 0) lb_publish(a.lb_status, k, k == 0 ? kLbInclusive : kLbAggregate, 0);
         }
         return;
     }

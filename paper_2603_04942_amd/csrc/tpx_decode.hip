@@ -1,14 +1,17 @@
 // Decode, unwrap and shot assignment (Sec. III; Sec. IV, ToA Unwrapping and
-// Eliminating Background Counts) as three passes over 4096-word tiles:
+// Eliminating Background Counts) as passes over 4096-word tiles:
 //   k_tile_summary  per tile: folded pixel / trigger counter runs and the
 //                   trigger words in stream order (one read of the packets);
-//   k_tile_scan     one workgroup folds the tile summaries into the state in
-//                   force at the start of every tile;
-//   k_trig_unwrap   unwraps the trigger words into the trigger table;
+//   k_tile_scan1/2  fold the tile summaries into the state in force at the
+//                   start of every tile (blocks of 1024 tiles, then blocks);
+//   k_trig_unwrap   one thread per tile: its entry state, and its trigger
+//                   words unwrapped into the trigger table;
 //   k_assign        second read of the packets: unwraps each pixel, finds its
-//                   shot (latest trigger at or before it), applies the ToF
-//                   cut and writes the kept events in stream order (stable
-//                   compaction with a decoupled look-back over tiles).
+//                   shot (latest trigger at or before it) in a slice of the
+//                   trigger table staged in LDS, applies the ToF cut and
+//                   writes the kept events in stream order (stable compaction
+//                   with a decoupled look-back over tiles that also checks
+//                   that kept events are in shot order).
 #include "tpx_kernels.h"
 
 namespace tpx {
@@ -17,6 +20,9 @@ namespace tpx {
 // consecutive words: padded by one word per 16 to spread LDS banks.
 __device__ inline int tile_slot(int i) { return i + (i >> 4); }
 constexpr int kTileLds = kTilePkts + kTilePkts / 16;
+constexpr int kWaves = kTileThreads / 64;
+constexpr uint64_t kTrigMargin = 64;   // triggers staged before / after a tile's own
+constexpr int kScanTiles = 1024;       // tiles per block of the first scan level
 
 __device__ inline void load_tile(const uint64_t* __restrict__ pk, uint64_t base, uint64_t n,
                                  uint64_t* sp) {
@@ -28,64 +34,112 @@ __device__ inline void load_tile(const uint64_t* __restrict__ pk, uint64_t base,
     }
 }
 
-// Exclusive in-order fold of one RunSum per thread (256 threads) through LDS.
-// Returns the fold of all threads before the caller; *all gets the total.
-__device__ inline RunSum wg_run_exscan(RunSum v, RunSum* buf, uint64_t jump, RunSum* all) {
-    const int t = threadIdx.x;
-    buf[t] = v;
-    __syncthreads();
-    if (t < 64) {  // each lane folds 4 consecutive entries, lane 0 folds lanes
-        RunSum a = run_empty();
-        for (int k = 0; k < 4; ++k) a = run_combine(a, buf[t * 4 + k], jump);
-        buf[256 + t] = a;
-    }
-    __syncthreads();
-    if (t == 0) {
-        RunSum a = run_empty();
-        for (int k = 0; k < 64; ++k) {
-            const RunSum c = buf[256 + k];
-            buf[256 + k] = a;  // exclusive
-            a = run_combine(a, c, jump);
-        }
-        buf[320] = a;
-    }
-    __syncthreads();
-    RunSum pre = buf[256 + (t >> 2)];
-    for (int k = (t & ~3); k < t; ++k) pre = run_combine(pre, buf[k], jump);
-    *all = buf[320];
-    __syncthreads();
-    return pre;
+// ------------------------------------------------------------- in-order folds
+__device__ inline RunSum run_push(RunSum r, uint64_t raw, uint64_t jump) {
+    if (r.count) r.sum += jump_of(r.last, raw, jump); else r.first = raw;
+    r.last = raw;
+    ++r.count;
+    return r;
 }
 
+__device__ inline RunSum shfl_up_run(const RunSum& v, int d) {
+    RunSum o;
+    o.first = __shfl_up(v.first, d, 64);
+    o.last = __shfl_up(v.last, d, 64);
+    o.sum = __shfl_up(v.sum, d, 64);
+    o.count = __shfl_up(v.count, d, 64);
+    return o;
+}
+
+__device__ inline TileAcc shfl_up_acc(const TileAcc& v, int d) {
+    return TileAcc{shfl_up_run(v.pix, d), shfl_up_run(v.tdc, d), __shfl_up(v.ntrig, d, 64)};
+}
+
+// Inclusive in-order fold over the lanes of a wave (Kogge-Stone).
+__device__ inline RunSum wave_run_inscan(RunSum v, uint64_t jump) {
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const RunSum o = shfl_up_run(v, d);
+        if ((int)__lane_id() >= d) v = run_combine(o, v, jump);
+    }
+    return v;
+}
+
+__device__ inline TileAcc wave_acc_inscan(TileAcc v, uint64_t jump) {
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const TileAcc o = shfl_up_acc(v, d);
+        if ((int)__lane_id() >= d) v = acc_combine(o, v, jump);
+    }
+    return v;
+}
+
+// Exclusive in-order fold of one RunSum per thread over the workgroup; *all
+// gets the fold of every thread.  wbuf holds one entry per wave.
+__device__ inline RunSum wg_run_exscan(RunSum v, RunSum* wbuf, uint64_t jump, RunSum* all) {
+    const RunSum inc = wave_run_inscan(v, jump);
+    RunSum ex = shfl_up_run(inc, 1);
+    if (__lane_id() == 0) ex = run_empty();
+    const int w = threadIdx.x >> 6;
+    if (__lane_id() == 63) wbuf[w] = inc;
+    __syncthreads();
+    RunSum pre = run_empty(), tot = run_empty();
+#pragma unroll
+    for (int k = 0; k < kWaves; ++k) {
+        const RunSum c = wbuf[k];
+        if (k < w) pre = run_combine(pre, c, jump);
+        tot = run_combine(tot, c, jump);
+    }
+    __syncthreads();
+    *all = tot;
+    return run_combine(pre, ex, jump);
+}
+
+// Exclusive in-order fold of one TileAcc per thread over 1024 threads.
+__device__ inline TileAcc wg1024_acc_exscan(TileAcc v, TileAcc* wbuf, uint64_t jump,
+                                            TileAcc* all) {
+    const TileAcc inc = wave_acc_inscan(v, jump);
+    TileAcc ex = shfl_up_acc(inc, 1);
+    if (__lane_id() == 0) ex = acc_empty();
+    const int w = threadIdx.x >> 6;
+    if (__lane_id() == 63) wbuf[w] = inc;
+    __syncthreads();
+    TileAcc pre = acc_empty(), tot = acc_empty();
+    for (int k = 0; k < 16; ++k) {
+        const TileAcc c = wbuf[k];
+        if (k < w) pre = acc_combine(pre, c, jump);
+        tot = acc_combine(tot, c, jump);
+    }
+    __syncthreads();
+    *all = tot;
+    return acc_combine(pre, ex, jump);
+}
+
+// ------------------------------------------------------------------ summary
 __global__ __launch_bounds__(kTileThreads) void k_tile_summary(const uint64_t* __restrict__ pk,
                                                               uint64_t n, uint32_t sub,
-                                                              uint64_t jump, TileSum* sums,
-                                                              uint64_t* tdc_slot,
-                                                              uint32_t* tdc_cnt) {
+                                                              uint64_t jump, TileAcc* sums,
+                                                              uint64_t* tdc_slot) {
     __shared__ uint64_t sp[kTileLds];
-    __shared__ RunSum buf[321];
-    __shared__ uint32_t tmp[kTileThreads / 64 + 1];
+    __shared__ RunSum wbuf[kWaves];
+    __shared__ uint32_t tmp[kWaves + 1];
     const uint64_t tile = blockIdx.x;
     const uint64_t base = tile * kTilePkts;
     load_tile(pk, base, n, sp);
     __syncthreads();
     const int nvalid = (int)min<uint64_t>((uint64_t)kTilePkts, n - base);
     RunSum P = run_empty(), T = run_empty();
-    uint32_t nt = 0;
 #pragma unroll
     for (int j = 0; j < kTileItems; ++j) {
         const int i = threadIdx.x * kTileItems + j;
         if (i < nvalid) {
             const Word d = decode_word(sp[tile_slot(i)], sub);
-            if (d.kind == kPixel) {
-                P = run_combine(P, RunSum{d.raw, d.raw, 0, 1}, jump);
-            } else if (d.kind == kTrigger) {
-                T = run_combine(T, RunSum{d.raw, d.raw, 0, 1}, jump);
-                ++nt;
-            }
+            if (d.kind == kPixel) P = run_push(P, d.raw, jump);
+            else if (d.kind == kTrigger) T = run_push(T, d.raw, jump);
         }
     }
     uint32_t ntot;
+    const uint32_t nt = (uint32_t)T.count;
     const uint32_t pos = wg_count_scan<kTileThreads>(nt, tmp, &ntot);
     if (nt) {
         uint32_t q = 0;
@@ -98,110 +152,67 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_summary(const uint64_t* _
         }
     }
     RunSum ap, at;
-    wg_run_exscan(P, buf, jump, &ap);
-    wg_run_exscan(T, buf, jump, &at);
-    if (threadIdx.x == 0) {
-        sums[tile].pix = ap;
-        sums[tile].tdc = at;
-        tdc_cnt[tile] = ntot;
-    }
+    wg_run_exscan(P, wbuf, jump, &ap);
+    wg_run_exscan(T, wbuf, jump, &at);
+    if (threadIdx.x == 0) sums[tile] = TileAcc{ap, at, ntot};
 }
 
-// One workgroup of 1024 threads folds all tile summaries in order.
-__global__ __launch_bounds__(1024) void k_tile_scan(const TileSum* __restrict__ sums,
-                                                   const uint32_t* __restrict__ tdc_cnt,
-                                                   uint64_t ntiles, RunSum pix0, RunSum tdc0,
-                                                   int64_t pix_epoch0, int64_t tdc_epoch0,
-                                                   uint64_t jump, TileEntry* entries,
-                                                   DevResults* res) {
-    __shared__ TileSum agg[1024];
-    __shared__ uint64_t cnt[1024];
-    __shared__ TileSum grp[65];
-    __shared__ uint64_t gcnt[65];
-    const int t = threadIdx.x;
-    const uint64_t per = (ntiles + 1023) / 1024;
-    const uint64_t lo = min<uint64_t>(ntiles, (uint64_t)t * per);
-    const uint64_t hi = min<uint64_t>(ntiles, lo + per);
-    TileSum a{run_empty(), run_empty()};
-    uint64_t c = 0;
-    for (uint64_t k = lo; k < hi; ++k) {
-        a.pix = run_combine(a.pix, sums[k].pix, jump);
-        a.tdc = run_combine(a.tdc, sums[k].tdc, jump);
-        c += tdc_cnt[k];
-    }
-    agg[t] = a;
-    cnt[t] = c;
-    __syncthreads();
-    if (t < 64) {
-        TileSum g{run_empty(), run_empty()};
-        uint64_t gc = 0;
-        for (int k = 0; k < 16; ++k) {
-            const TileSum& e = agg[t * 16 + k];
-            g.pix = run_combine(g.pix, e.pix, jump);
-            g.tdc = run_combine(g.tdc, e.tdc, jump);
-            gc += cnt[t * 16 + k];
-        }
-        grp[t] = g;
-        gcnt[t] = gc;
-    }
-    __syncthreads();
-    if (t == 0) {
-        TileSum run{pix0, tdc0};
-        uint64_t rc = 0;
-        for (int k = 0; k < 64; ++k) {
-            const TileSum g = grp[k];
-            const uint64_t gc = gcnt[k];
-            grp[k] = run;
-            gcnt[k] = rc;
-            run.pix = run_combine(run.pix, g.pix, jump);
-            run.tdc = run_combine(run.tdc, g.tdc, jump);
-            rc += gc;
-        }
-        grp[64] = run;
-        gcnt[64] = rc;
-    }
-    __syncthreads();
-    TileSum pre = grp[t >> 4];
-    uint64_t pc = gcnt[t >> 4];
-    for (int k = t & ~15; k < t; ++k) {
-        pre.pix = run_combine(pre.pix, agg[k].pix, jump);
-        pre.tdc = run_combine(pre.tdc, agg[k].tdc, jump);
-        pc += cnt[k];
-    }
-    for (uint64_t k = lo; k < hi; ++k) {
-        TileEntry e;
-        e.pix = pre.pix;
-        e.tdc = pre.tdc;
-        e.pix_epoch = pix_epoch0 + pre.pix.sum;
-        e.tdc_epoch = tdc_epoch0 + pre.tdc.sum;
-        e.trig_off = pc;
-        entries[k] = e;
-        pre.pix = run_combine(pre.pix, sums[k].pix, jump);
-        pre.tdc = run_combine(pre.tdc, sums[k].tdc, jump);
-        pc += tdc_cnt[k];
-    }
-    if (t == 0) {
-        const TileSum all = grp[64];
-        res->pix_epoch_end = pix_epoch0 + all.pix.sum;
-        res->tdc_epoch_end = tdc_epoch0 + all.tdc.sum;
+// -------------------------------------------------------------- tile prefix
+// First level: exclusive fold of the tiles inside each block of 1024 tiles
+// (partial) and the fold of every block (blk[b]).
+__global__ __launch_bounds__(1024) void k_tile_scan1(const TileAcc* __restrict__ sums,
+                                                    uint64_t ntiles, uint64_t jump,
+                                                    TileAcc* partial, TileAcc* blk) {
+    __shared__ TileAcc wbuf[16];
+    const uint64_t t = (uint64_t)blockIdx.x * kScanTiles + threadIdx.x;
+    const TileAcc v = t < ntiles ? sums[t] : acc_empty();
+    TileAcc all;
+    const TileAcc ex = wg1024_acc_exscan(v, wbuf, jump, &all);
+    if (t < ntiles) partial[t] = ex;
+    if (threadIdx.x == 0) blk[blockIdx.x] = all;
+}
+
+// Second level (one workgroup): state in force at the start of every block,
+// blk[nblk + b], and the state at the end of the call.
+__global__ __launch_bounds__(1024) void k_tile_scan2(TileAcc* blk, uint64_t nblk, TileAcc init,
+                                                    int64_t pe0, int64_t te0, uint64_t jump,
+                                                    DevResults* res) {
+    __shared__ TileAcc wbuf[16];
+    const uint64_t b = threadIdx.x;
+    TileAcc v = b < nblk ? blk[b] : acc_empty();
+    if (b == 0) v = acc_combine(init, v, jump);
+    TileAcc all;
+    TileAcc ex = wg1024_acc_exscan(v, wbuf, jump, &all);
+    if (b == 0) ex = init;
+    if (b < nblk) blk[nblk + b] = ex;
+    if (b == 0) {
+        res->pix_epoch_end = pe0 + all.pix.sum;
+        res->tdc_epoch_end = te0 + all.tdc.sum;
         res->pix_last_end = all.pix.last;
         res->tdc_last_end = all.tdc.last;
         res->pix_has_end = all.pix.count > 0;
         res->tdc_has_end = all.tdc.count > 0;
-        res->n_trig = gcnt[64];
+        res->n_trig = all.ntrig - init.ntrig;
     }
 }
 
-// One thread per tile unwraps that tile's trigger words in order.
-__global__ void k_trig_unwrap(const TileEntry* __restrict__ entries,
-                              const uint32_t* __restrict__ tdc_cnt,
-                              const uint64_t* __restrict__ tdc_slot, uint64_t ntiles,
-                              uint64_t jump, uint64_t* tab, DevResults* res) {
+// One thread per tile: its entry state, then its trigger words in order.
+__global__ void k_trig_unwrap(const TileAcc* __restrict__ sums, const TileAcc* __restrict__ partial,
+                              const TileAcc* __restrict__ blk, const uint64_t* __restrict__ tdc_slot,
+                              uint64_t ntiles, uint64_t nblk, int64_t pe0, int64_t te0,
+                              uint64_t jump, TileEntry* entries, uint64_t* tab, DevResults* res) {
     const uint64_t tile = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (tile >= ntiles) return;
-    const uint32_t c = tdc_cnt[tile];
+    const TileAcc pre = acc_combine(blk[nblk + tile / kScanTiles], partial[tile], jump);
+    TileEntry e;
+    e.pix = pre.pix;
+    e.tdc = pre.tdc;
+    e.pix_epoch = pe0 + pre.pix.sum;
+    e.tdc_epoch = te0 + pre.tdc.sum;
+    e.trig_off = pre.ntrig - blk[nblk].ntrig;  // init.ntrig is the front of block 0
+    entries[tile] = e;
+    const uint32_t c = (uint32_t)sums[tile].ntrig;
     if (c == 0) return;
-    const TileEntry e = entries[tile];
     bool has = e.tdc.count > 0;
     uint64_t last = e.tdc.last;
     int64_t epoch = e.tdc_epoch;
@@ -243,28 +254,35 @@ __device__ inline uint64_t upper_bound_u64(P a, uint64_t lo, uint64_t hi, uint64
     return lo;
 }
 
+// ------------------------------------------------------------------- assign
 template <bool kSoA>
 __global__ __launch_bounds__(kTileThreads) void k_assign(AssignArgs a) {
     __shared__ uint64_t sp[kTileLds];
-    __shared__ RunSum buf[321];
-    __shared__ uint64_t slice[kTrigSlice];
-    __shared__ uint32_t tmp[kTileThreads / 64 + 1];
-    __shared__ uint64_t bcast[8];
-    __shared__ uint32_t gmin_s[kTileThreads], gmax_s[kTileThreads];
-    __shared__ uint32_t unsorted_s;
+    __shared__ uint64_t slice[kTrigSlice + 1];
+    __shared__ RunSum wbuf[kWaves];
+    __shared__ uint32_t w_cnt[kWaves], w_max[kWaves], w_min[kWaves];
+    __shared__ unsigned long long w_stat[kWaves][8];
+    __shared__ uint64_t bcast[2];
+    constexpr uint32_t kNo = 0xFFFFFFFFu;
 
-    if (threadIdx.x == 0) {
-        bcast[0] = atomicAdd(&a.res->tile_ticket, 1ull);
-        unsorted_s = 0;
-    }
+    if (threadIdx.x == 0) bcast[0] = atomicAdd(&a.res->tile_ticket, 1ull);
     __syncthreads();
-    const uint64_t tile = bcast[0];
-    const uint64_t base = tile * kTilePkts;
+    const uint32_t tile = __builtin_amdgcn_readfirstlane((uint32_t)bcast[0]);
+    const uint64_t base = (uint64_t)tile * kTilePkts;
     load_tile(a.pk, base, a.n, sp);
-    __syncthreads();
-    const int nvalid = (int)min<uint64_t>((uint64_t)kTilePkts, a.n - base);
     const TileEntry e = a.entries[tile];
     const uint64_t n_tab = a.n_win + *a.n_trig_dev;
+    // slice of the trigger table around this tile's own trigger words
+    const uint64_t t0 = a.n_win + e.trig_off;
+    const uint64_t s_lo = t0 > kTrigMargin ? t0 - kTrigMargin : 0;
+    uint64_t s_hi = min<uint64_t>(n_tab, t0 + a.sums[tile].ntrig + kTrigMargin);
+    s_hi = min<uint64_t>(s_hi, s_lo + kTrigSlice);
+    const uint32_t len = (uint32_t)(s_hi - s_lo);
+    const bool has_above = s_hi < n_tab;  // slice[len] = tab[s_hi]
+    for (uint32_t k = threadIdx.x; k < len + (has_above ? 1u : 0u); k += kTileThreads)
+        slice[k] = a.tab[s_lo + k];
+    __syncthreads();
+    const int nvalid = (int)min<uint64_t>((uint64_t)kTilePkts, a.n - base);
 
     // this thread's run of pixel counter values, folded across the workgroup
     RunSum P = run_empty();
@@ -273,19 +291,20 @@ __global__ __launch_bounds__(kTileThreads) void k_assign(AssignArgs a) {
         const int i = threadIdx.x * kTileItems + j;
         if (i < nvalid) {
             const Word d = decode_word(sp[tile_slot(i)], a.sub);
-            if (d.kind == kPixel) P = run_combine(P, RunSum{d.raw, d.raw, 0, 1}, a.jump);
+            if (d.kind == kPixel) P = run_push(P, d.raw, a.jump);
         }
     }
     RunSum all;
-    const RunSum pre = run_combine(e.pix, wg_run_exscan(P, buf, a.jump, &all), a.jump);
+    const RunSum pre = run_combine(e.pix, wg_run_exscan(P, wbuf, a.jump, &all), a.jump);
 
     // unwrap this thread's pixels
     uint64_t tv[kTileItems];
     bool has = pre.count > 0;
     uint64_t last = pre.last;
     int64_t epoch = e.pix_epoch + (pre.sum - e.pix.sum);
-    uint64_t tmin = ~0ull, tmax = 0;
-    unsigned long long fwd = 0, back = 0, npix = 0, nother = 0, err = 0;
+    uint64_t tmax1 = 0;
+    uint32_t fwd = 0, back = 0, npix = 0, nother = 0;
+    unsigned long long err = 0;
 #pragma unroll
     for (int j = 0; j < kTileItems; ++j) {
         const int i = threadIdx.x * kTileItems + j;
@@ -306,8 +325,7 @@ __global__ __launch_bounds__(kTileThreads) void k_assign(AssignArgs a) {
                     err |= kErrStream;
                 } else {
                     tv[j] = d.raw + (uint64_t)epoch * kPixPeriod;
-                    tmin = min(tmin, tv[j]);
-                    tmax = max(tmax, tv[j]);
+                    tmax1 = max(tmax1, tv[j] + 1);
                 }
             } else if (d.kind == kOther) {
                 ++nother;
@@ -315,67 +333,36 @@ __global__ __launch_bounds__(kTileThreads) void k_assign(AssignArgs a) {
         }
     }
 
-    // time range of the tile's pixels -> slice of the trigger table in LDS
-    {
-        uint64_t mn = tmin, mx = tmax;
-        for (int d = 32; d > 0; d >>= 1) {
-            mn = min(mn, (uint64_t)__shfl_xor(mn, d, 64));
-            mx = max(mx, (uint64_t)__shfl_xor(mx, d, 64));
-        }
-        if (__lane_id() == 0) {
-            reinterpret_cast<uint64_t*>(gmin_s)[threadIdx.x >> 6] = mn;
-            reinterpret_cast<uint64_t*>(gmax_s)[threadIdx.x >> 6] = mx;
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            for (int w = 1; w < kTileThreads / 64; ++w) {
-                mn = min(mn, reinterpret_cast<uint64_t*>(gmin_s)[w]);
-                mx = max(mx, reinterpret_cast<uint64_t*>(gmax_s)[w]);
-            }
-            uint64_t s_lo = 0, s_hi = 0, use = 0;
-            if (mn <= mx && n_tab > 0) {
-                const uint64_t ulo = upper_bound_u64(a.tab, 0, n_tab, mn);
-                const uint64_t uhi = upper_bound_u64(a.tab, ulo, n_tab, mx);
-                s_lo = ulo > 0 ? ulo - 1 : 0;
-                s_hi = uhi;  // exclusive end of the candidate shots + 1
-                if (s_hi - s_lo <= (uint64_t)kTrigSlice) use = 1;
-            }
-            bcast[1] = s_lo;
-            bcast[2] = s_hi;
-            bcast[3] = use;
-        }
-        __syncthreads();
-    }
-    const uint64_t s_lo = bcast[1], s_hi = bcast[2];
-    const bool use_slice = bcast[3] != 0;
-    if (use_slice) {
-        for (uint64_t k = threadIdx.x; k < s_hi - s_lo; k += kTileThreads) slice[k] = a.tab[s_lo + k];
-    }
-    __syncthreads();
-
-    // shot of each pixel, cut, keep
+    // shot of each pixel (latest trigger at or before it), cut, keep
     uint32_t sv[kTileItems];
-    uint32_t nkeep = 0;
-    unsigned long long npre = 0, ncut = 0, nlate = 0;
-    uint32_t first_s = 0xFFFFFFFFu, last_s = 0;
+    uint32_t nkeep = 0, npre = 0, ncut = 0, nlate = 0;
+    uint32_t first_s = kNo, last_s = 0;
     bool sorted = true;
+    uint32_t hint = 0;
 #pragma unroll
     for (int j = 0; j < kTileItems; ++j) {
-        sv[j] = 0xFFFFFFFFu;
+        sv[j] = kNo;
         if (tv[j] != ~0ull) {
             const uint64_t t = tv[j];
-            uint64_t ub;
-            if (use_slice) {
-                ub = s_lo + upper_bound_u64(slice, 0, s_hi - s_lo, t);
-                if (ub == s_lo && s_lo > 0) ub = upper_bound_u64(a.tab, 0, s_lo, t);
+            uint64_t ub, trig;
+            const bool below = s_lo > 0 && t < slice[0];
+            const bool above = has_above && t >= slice[len];
+            if (!below && !above) {
+                // entries before the slice are <= t, entries after it are > t
+                const bool ok = (hint == 0 || slice[hint - 1] <= t) && (hint == len || t < slice[hint]);
+                if (!ok) hint = (uint32_t)upper_bound_u64(slice, 0, len, t);
+                ub = s_lo + hint;
+                trig = hint ? slice[hint - 1] : 0;
             } else {
                 ub = upper_bound_u64(a.tab, 0, n_tab, t);
+                trig = ub ? a.tab[ub - 1] : 0;
             }
+            tv[j] = ~0ull;
             if (ub == 0) {
                 if (a.tab_has_before) ++nlate; else ++npre;
             } else {
                 const uint64_t s = ub - 1;
-                const uint64_t tof = t - a.tab[s];
+                const uint64_t tof = t - trig;
                 if (tof > a.tof_max) {
                     ++ncut;
                 } else if (s < a.first_open) {
@@ -383,132 +370,195 @@ __global__ __launch_bounds__(kTileThreads) void k_assign(AssignArgs a) {
                 } else {
                     sv[j] = (uint32_t)s;
                     ++nkeep;
-                    if (first_s == 0xFFFFFFFFu) first_s = (uint32_t)s;
+                    if (first_s == kNo) first_s = (uint32_t)s;
                     if ((uint32_t)s < last_s) sorted = false;
                     last_s = (uint32_t)s;
+                    if constexpr (kSoA) {
+                        tv[j] = t;
+                    } else {
+                        const Word d = decode_word(sp[tile_slot(threadIdx.x * kTileItems + j)], a.sub);
+                        tv[j] = pack_event(d.x, d.y, d.tot, (uint32_t)tof);
+                    }
                 }
             }
         }
     }
 
-    // stable compaction: thread prefix, tile total, look-back over tiles
-    uint32_t tile_keep;
-    const uint32_t tpre = wg_count_scan<kTileThreads>(nkeep, tmp, &tile_keep);
-    if (threadIdx.x == 0) {
-        if (tile == 0) {
-            lb_publish(a.lb_status, 0, kLbInclusive, tile_keep);
-            bcast[4] = 0;
-        } else {
-            lb_publish(a.lb_status, tile, kLbAggregate, tile_keep);
-            const uint64_t p = lb_lookback(a.lb_status, tile, &a.res->err);
-            lb_publish(a.lb_status, tile, kLbInclusive, p + tile_keep);
-            bcast[4] = p;
-        }
-    }
-    // order check across threads: a thread's first kept shot must not be
-    // below the last kept shot of any earlier thread
-    gmin_s[threadIdx.x] = nkeep ? first_s : 0xFFFFFFFFu;
-    gmax_s[threadIdx.x] = nkeep ? last_s : 0u;
-    if (!sorted) atomicOr(&unsorted_s, 1u);
-    __syncthreads();
-    const uint64_t out0 = a.ev_off + bcast[4] + tpre;
-    if (threadIdx.x == 0) {
-        uint32_t run_max = 0, any = 0, f = 0xFFFFFFFFu;
-        bool ok = true;
-        for (int k = 0; k < kTileThreads; ++k) {
-            if (gmin_s[k] == 0xFFFFFFFFu) continue;
-            if (any && gmin_s[k] < run_max) ok = false;
-            if (!any) f = gmin_s[k];
-            any = 1;
-            run_max = max(run_max, gmax_s[k]);
-        }
-        if (a.recs) {
-            TileRec r;
-            r.first_g = f;
-            r.last_g = run_max;
-            r.n_kept = tile_keep;
-            r.sorted = (ok && unsorted_s == 0) ? 1u : 0u;
-            a.recs[tile] = r;
-        }
-    }
-
-    // write kept events in stream order; count events per shot
-    uint64_t o = out0;
-    uint32_t run_s = 0xFFFFFFFFu, run_n = 0;
+    // workgroup: kept-event prefix, running max of kept shots (order check),
+    // smallest kept shot, statistics
+    const int w = threadIdx.x >> 6;
+    const uint32_t m1 = nkeep ? last_s + 1 : 0;
+    uint32_t cinc = nkeep, minc = m1, fmin = nkeep ? first_s : kNo;
 #pragma unroll
-    for (int j = 0; j < kTileItems; ++j) {
-        if (sv[j] != 0xFFFFFFFFu) {
-            const int i = threadIdx.x * kTileItems + j;
-            const Word d = decode_word(sp[tile_slot(i)], a.sub);
-            const uint64_t s = sv[j];
-            if (o < a.ev_cap) {
-                if constexpr (kSoA) {
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t oc = __shfl_up(cinc, d, 64), om = __shfl_up(minc, d, 64);
+        if ((int)__lane_id() >= d) {
+            cinc += oc;
+            minc = max(minc, om);
+        }
+        fmin = min(fmin, (uint32_t)__shfl_xor(fmin, d, 64));
+    }
+    uint32_t stat[8] = {npix, nother, npre, ncut, nlate, fwd, back, 0};
+#pragma unroll
+    for (int k = 0; k < 7; ++k)
+        for (int d = 32; d > 0; d >>= 1) stat[k] += __shfl_xor(stat[k], d, 64);
+    uint64_t tm = tmax1;
+    for (int d = 32; d > 0; d >>= 1) tm = max(tm, (uint64_t)__shfl_xor(tm, d, 64));
+    if (__lane_id() == 63) {
+        w_cnt[w] = cinc;
+        w_max[w] = minc;
+    }
+    if (__lane_id() == 0) {
+        w_min[w] = fmin;
+#pragma unroll
+        for (int k = 0; k < 7; ++k) w_stat[w][k] = stat[k];
+        w_stat[w][7] = tm;
+    }
+    uint32_t mex_w = __shfl_up(minc, 1, 64);
+    if (__lane_id() == 0) mex_w = 0;
+    __syncthreads();
+    uint32_t tpre = cinc - nkeep, mex = mex_w, tile_keep = 0, tile_max1 = 0, tile_min = kNo;
+#pragma unroll
+    for (int k = 0; k < kWaves; ++k) {
+        if (k < w) {
+            tpre += w_cnt[k];
+            mex = max(mex, w_max[k]);
+        }
+        tile_keep += w_cnt[k];
+        tile_max1 = max(tile_max1, w_max[k]);
+        tile_min = min(tile_min, w_min[k]);
+    }
+    const bool bad = !sorted || (nkeep && first_s + 1 < mex);
+    const bool tile_bad = __syncthreads_or(bad) != 0;
+
+    // look-back over tiles: kept events and largest kept shot before this tile
+    if (w == 0) {
+        const uint64_t mine = (uint64_t)tile_keep | ((uint64_t)tile_max1 << 31);
+        uint64_t prefix;
+        if (tile == 0) {
+            prefix = a.carry_last1 << 31;
+        } else {
+            if (__lane_id() == 0) lb_publish(a.lb_status, tile, kLbAggregate, mine);
+            prefix = lb_lookback_wave<LbCountMax>(a.lb_status, tile, &a.res->err);
+        }
+        if (__lane_id() == 0) {
+            lb_publish(a.lb_status, tile, kLbInclusive, LbCountMax::op(prefix, mine));
+            bcast[1] = prefix;
+            const uint64_t prev_max1 = prefix >> 31;
+            if (tile_bad || (tile_keep && prev_max1 > (uint64_t)tile_min + 1))
+                atomicOr(&a.res->unsorted, 1ull);
+            unsigned long long* dst[7] = {&a.res->n_pixels, &a.res->n_other, &a.res->n_pre_trigger,
+                                          &a.res->n_tof_cut, &a.res->n_late_drop,
+                                          &a.res->n_pix_wraps, &a.res->n_pix_backjumps};
+#pragma unroll
+            for (int k = 0; k < 7; ++k) {
+                unsigned long long v = 0;
+                for (int q = 0; q < kWaves; ++q) v += w_stat[q][k];
+                if (v) atomicAdd(dst[k], v);
+            }
+            unsigned long long mx = 0;
+            for (int q = 0; q < kWaves; ++q) mx = max(mx, w_stat[q][7]);
+            if (mx) atomicMax(&a.res->max_t_plus1, mx);
+            if (tile_keep) atomicAdd(&a.res->n_kept, (unsigned long long)tile_keep);
+        }
+    }
+    if (err) atomicOr(&a.res->err, err);
+    __syncthreads();
+    const uint64_t pcount = bcast[1] & LbCountMax::kLow;
+    const uint64_t out0 = a.ev_off + pcount;
+
+    if constexpr (kSoA) {
+        uint64_t o = out0 + tpre;
+#pragma unroll
+        for (int j = 0; j < kTileItems; ++j) {
+            if (sv[j] != kNo) {
+                if (o < a.ev_cap) {
+                    const Word d = decode_word(sp[tile_slot(threadIdx.x * kTileItems + j)], a.sub);
                     a.soa.x[o] = (uint16_t)d.x;
                     a.soa.y[o] = (uint16_t)d.y;
                     a.soa.tot[o] = (uint16_t)d.tot;
-                    a.soa.shot[o] = (uint32_t)(a.shot_base + s);
+                    a.soa.shot[o] = (uint32_t)(a.shot_base + sv[j]);
                     a.soa.toa[o] = tv[j];
-                } else {
-                    a.ev[o] = pack_event(d.x, d.y, d.tot, (uint32_t)(tv[j] - a.tab[s]));
-                    if (a.shot_out) a.shot_out[o] = (uint32_t)s;
                 }
-            }
-            ++o;
-            if (a.shot_cnt) {
-                if ((uint32_t)s != run_s) {
-                    if (run_n) atomicAdd(&a.shot_cnt[run_s], run_n);
-                    run_s = (uint32_t)s;
-                    run_n = 0;
-                }
-                ++run_n;
+                ++o;
             }
         }
-    }
-    if (a.shot_cnt && run_n) atomicAdd(&a.shot_cnt[run_s], run_n);
-
-    // statistics
-    const unsigned long long vals[7] = {npix, nother, npre, ncut, nlate, fwd, back};
-    unsigned long long* dst[7] = {&a.res->n_pixels, &a.res->n_other, &a.res->n_pre_trigger,
-                                  &a.res->n_tof_cut, &a.res->n_late_drop, &a.res->n_pix_wraps,
-                                  &a.res->n_pix_backjumps};
+    } else {
+        // kept events staged in LDS in output order, then written contiguously
+        {
+            uint32_t q = tpre;
 #pragma unroll
-    for (int k = 0; k < 7; ++k) {
-        unsigned long long v = vals[k];
-        for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
-        if (__lane_id() == 0 && v) atomicAdd(dst[k], v);
+            for (int j = 0; j < kTileItems; ++j)
+                if (sv[j] != kNo) sp[tile_slot(q++)] = tv[j];
+        }
+        __syncthreads();
+        for (uint32_t k = threadIdx.x; k < tile_keep; k += kTileThreads)
+            if (out0 + k < a.ev_cap) a.ev[out0 + k] = sp[tile_slot(k)];
+        if (a.shot_out) {
+            __syncthreads();
+            uint32_t q = tpre;
+#pragma unroll
+            for (int j = 0; j < kTileItems; ++j)
+                if (sv[j] != kNo) sp[tile_slot(q++)] = sv[j];
+            __syncthreads();
+            for (uint32_t k = threadIdx.x; k < tile_keep; k += kTileThreads)
+                if (out0 + k < a.ev_cap) a.shot_out[out0 + k] = (uint32_t)sp[tile_slot(k)];
+        }
+        // events per shot from run boundaries: a run of shot s over positions
+        // [p, p') adds p' - p to its count.  Exact when the kept events are in
+        // shot order (otherwise the caller takes the sorting path).
+        if (a.shot_cnt && nkeep) {
+            uint32_t prev = mex;  // previous kept shot in the tile + 1, 0 = none
+            uint32_t p = (uint32_t)(pcount + tpre);
+#pragma unroll
+            for (int j = 0; j < kTileItems; ++j) {
+                const uint32_t s = sv[j];
+                if (s != kNo) {
+                    if (prev == 0) {
+                        atomicAdd(&a.shot_cnt[s], 0u - p);
+                    } else if (prev - 1 != s) {
+                        atomicAdd(&a.shot_cnt[prev - 1], p);
+                        atomicAdd(&a.shot_cnt[s], 0u - p);
+                    }
+                    prev = s + 1;
+                    ++p;
+                }
+            }
+            if (tpre + nkeep == tile_keep) atomicAdd(&a.shot_cnt[prev - 1], p);
+        }
     }
-    {
-        uint64_t mx = tmax;
-        if (tmin > tmax) mx = 0;
-        for (int d = 32; d > 0; d >>= 1) mx = max(mx, (uint64_t)__shfl_xor(mx, d, 64));
-        if (__lane_id() == 0 && mx) atomicMax(&a.res->max_t_plus1, (unsigned long long)(mx + 1));
-    }
-    if (err) atomicOr(&a.res->err, err);
-    if (threadIdx.x == 0) atomicAdd(&a.res->n_kept, (unsigned long long)tile_keep);
 }
 
 // -------------------------------------------------------------- launchers
 void launch_tile_summary(const uint64_t* pk, uint64_t n, uint32_t sub, uint64_t jump,
-                         TileSum* sums, uint64_t* tdc_slot, uint32_t* tdc_cnt, hipStream_t s) {
+                         TileAcc* sums, uint64_t* tdc_slot, hipStream_t s) {
     const uint64_t ntiles = (n + kTilePkts - 1) / kTilePkts;
     if (ntiles == 0) return;
     hipLaunchKernelGGL(k_tile_summary, dim3((unsigned)ntiles), dim3(kTileThreads), 0, s, pk, n,
-                       sub, jump, sums, tdc_slot, tdc_cnt);
+                       sub, jump, sums, tdc_slot);
 }
 
-void launch_tile_scan(const TileSum* sums, const uint32_t* tdc_cnt, uint64_t ntiles, RunSum pix0,
-                      RunSum tdc0, int64_t pe0, int64_t te0, uint64_t jump, TileEntry* entries,
-                      DevResults* res, hipStream_t s) {
-    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, s, sums, tdc_cnt, ntiles, pix0, tdc0,
-                       pe0, te0, jump, entries, res);
+uint64_t tile_scan_blocks(uint64_t ntiles) { return (ntiles + kScanTiles - 1) / kScanTiles; }
+
+void launch_tile_scan(const TileAcc* sums, uint64_t ntiles, TileAcc init, int64_t pe0, int64_t te0,
+                      uint64_t jump, TileAcc* partial, TileAcc* blk, DevResults* res,
+                      hipStream_t s) {
+    const uint64_t nblk = tile_scan_blocks(ntiles);
+    if (nblk)
+        hipLaunchKernelGGL(k_tile_scan1, dim3((unsigned)nblk), dim3(kScanTiles), 0, s, sums, ntiles,
+                           jump, partial, blk);
+    hipLaunchKernelGGL(k_tile_scan2, dim3(1), dim3(1024), 0, s, blk, nblk, init, pe0, te0, jump,
+                       res);
 }
 
-void launch_trig_unwrap(const TileEntry* entries, const uint32_t* tdc_cnt, const uint64_t* slot,
-                        uint64_t ntiles, uint64_t jump, uint64_t* tab, DevResults* res,
+void launch_trig_unwrap(const TileAcc* sums, const TileAcc* partial, const TileAcc* blk,
+                        const uint64_t* slot, uint64_t ntiles, int64_t pe0, int64_t te0,
+                        uint64_t jump, TileEntry* entries, uint64_t* tab, DevResults* res,
                         hipStream_t s) {
     if (ntiles == 0) return;
     hipLaunchKernelGGL(k_trig_unwrap, dim3((unsigned)((ntiles + 255) / 256)), dim3(256), 0, s,
-                       entries, tdc_cnt, slot, ntiles, jump, tab, res);
+                       sums, partial, blk, slot, ntiles, tile_scan_blocks(ntiles), pe0, te0, jump,
+                       entries, tab, res);
 }
 
 void launch_assign(const AssignArgs& a, bool soa, hipStream_t s) {

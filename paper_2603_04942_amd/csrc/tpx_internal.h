@@ -98,19 +98,23 @@ constexpr int kTileItems = 16;
 constexpr int kTilePkts = kTileThreads * kTileItems;  // 4096 words = 32 KB
 constexpr int kTrigSlice = 1024;                       // triggers staged in LDS
 
-struct TileSum {       // written by the summary pass
+// Fold of a run of tiles: pixel and trigger counter runs, trigger words.
+struct TileAcc {
     RunSum pix, tdc;
+    uint64_t ntrig;
 };
+
+__host__ __device__ inline TileAcc acc_empty() { return TileAcc{run_empty(), run_empty(), 0}; }
+
+__host__ __device__ inline TileAcc acc_combine(const TileAcc& a, const TileAcc& b, uint64_t jump) {
+    return TileAcc{run_combine(a.pix, b.pix, jump), run_combine(a.tdc, b.tdc, jump),
+                   a.ntrig + b.ntrig};
+}
 
 struct TileEntry {     // state in force at the start of a tile
     RunSum pix, tdc;   // everything before the tile, folded
     int64_t pix_epoch, tdc_epoch;
     uint64_t trig_off; // triggers before the tile (within this call)
-};
-
-struct TileRec {       // written by the assignment pass
-    uint32_t first_g, last_g;   // first / last kept shot index in the tile
-    uint32_t n_kept, sorted;    // sorted: kept shots never decrease in the tile
 };
 
 // Device-side results and counters of one call; read back with one copy.
@@ -158,25 +162,53 @@ __device__ inline void lb_publish(uint64_t* status, uint64_t idx, uint64_t flag,
     __hip_atomic_store(status + idx, flag | v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Exclusive prefix of the values of items 0..idx-1 (called by one thread).
-__device__ inline uint64_t lb_lookback(uint64_t* status, uint64_t idx, unsigned long long* err) {
+// Look-back value combiners: plain sums, and for tiles a kept-event count in
+// bits 0-30 with the largest kept shot + 1 in bits 31-61.
+struct LbSum {
+    __device__ static uint64_t op(uint64_t a, uint64_t b) { return a + b; }
+};
+struct LbCountMax {
+    static constexpr uint64_t kLow = (1ull << 31) - 1;
+    __device__ static uint64_t op(uint64_t a, uint64_t b) {
+        const uint64_t ha = a >> 31, hb = b >> 31;
+        return ((a & kLow) + (b & kLow)) | ((ha > hb ? ha : hb) << 31);
+    }
+};
+
+// Exclusive prefix of the values of items 0..idx-1, called by all 64 lanes of
+// one wave: each round reads the status words of the 64 nearest predecessors
+// at once and stops at the nearest inclusive one.  A round in which a word
+// needed so far is still unpublished is repeated (bounded; kErrSpin).
+template <class Op>
+__device__ inline uint64_t lb_lookback_wave(uint64_t* status, uint64_t idx, unsigned long long* err) {
+    const int l = (int)__lane_id();
     uint64_t acc = 0;
-    int64_t j = (int64_t)idx - 1;
+    int64_t base = (int64_t)idx - 1;
     uint64_t spins = 0;
-    while (j >= 0) {
-        const uint64_t s = __hip_atomic_load(status + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    while (base >= 0) {
+        const int64_t j = base - l;
+        const uint64_t s = j >= 0 ? __hip_atomic_load(status + j, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT)
+                                  : kLbInclusive;  // nothing before item 0
         const uint64_t f = s & ~kLbValueMask;
-        if (f == 0) {
+        const uint64_t incl = __ballot(f == kLbInclusive);
+        const uint64_t none = __ballot(f == 0);
+        const int fi = incl ? __ffsll((unsigned long long)incl) - 1 : 64;
+        const uint64_t need = fi >= 63 ? ~0ull : ((2ull << fi) - 1);
+        if (none & need) {
             if (++spins > kLbSpinLimit) {
-                atomicOr(err, (unsigned long long)kErrSpin);
+                if (l == 0) atomicOr(err, (unsigned long long)kErrSpin);
                 break;
             }
             __builtin_amdgcn_s_sleep(1);
             continue;
         }
-        acc += s & kLbValueMask;
-        if (f == kLbInclusive) break;
-        --j;
+        uint64_t v = l <= fi ? (s & kLbValueMask) : 0;
+#pragma unroll
+        for (int d = 32; d > 0; d >>= 1) v = Op::op(v, (uint64_t)__shfl_xor(v, d, 64));
+        acc = Op::op(acc, v);
+        if (fi < 64) break;
+        base -= 64;
     }
     return acc;
 }

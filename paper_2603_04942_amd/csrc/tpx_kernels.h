@@ -12,6 +12,7 @@ struct AssignArgs {
     uint32_t tof_max;
     uint64_t jump;
     const TileEntry* entries;
+    const TileAcc* sums;       // per-tile summaries (trigger count of each tile)
     const uint64_t* tab;       // trigger table: [window triggers..., new triggers...]
     uint64_t n_win;            // window triggers in front of this call's
     const unsigned long long* n_trig_dev;  // triggers decoded by this call
@@ -26,7 +27,7 @@ struct AssignArgs {
     // structure-of-arrays output (tpx_decode)
     tpx_events soa;
     uint64_t shot_base;        // global index of tab[0]
-    TileRec* recs;
+    uint64_t carry_last1;      // table index + 1 of the last event in front (0 = none)
     uint64_t* lb_status;       // zeroed, one word per tile
     DevResults* res;
 };
@@ -36,6 +37,7 @@ struct ClusterArgs {
     tpx_events soa;            // original events (event mode)
     const uint32_t* perm;      // group-order position -> original position, or null
     const uint32_t* grp_off;   // first position of each group, [n_grp + 1]
+    const uint32_t* seg_lo;    // first group of each segment, [n_seg + 1] (k_seg_table)
     const uint32_t* grp_shot;  // group -> table index (stream) or shot value; null = identity
     const unsigned long long* n_ev_dev;
     const unsigned long long* n_grp_dev;
@@ -58,15 +60,22 @@ struct ClusterArgs {
 };
 
 void launch_tile_summary(const uint64_t* pk, uint64_t n, uint32_t sub, uint64_t jump,
-                         TileSum* sums, uint64_t* tdc_slot, uint32_t* tdc_cnt, hipStream_t s);
-void launch_tile_scan(const TileSum* sums, const uint32_t* tdc_cnt, uint64_t ntiles, RunSum pix0,
-                      RunSum tdc0, int64_t pe0, int64_t te0, uint64_t jump, TileEntry* entries,
-                      DevResults* res, hipStream_t s);
-void launch_trig_unwrap(const TileEntry* entries, const uint32_t* tdc_cnt, const uint64_t* slot,
-                        uint64_t ntiles, uint64_t jump, uint64_t* tab, DevResults* res,
+                         TileAcc* sums, uint64_t* tdc_slot, hipStream_t s);
+// blk holds 2 * ceil(ntiles / 1024) entries
+void launch_tile_scan(const TileAcc* sums, uint64_t ntiles, TileAcc init, int64_t pe0, int64_t te0,
+                      uint64_t jump, TileAcc* partial, TileAcc* blk, DevResults* res, hipStream_t s);
+void launch_trig_unwrap(const TileAcc* sums, const TileAcc* partial, const TileAcc* blk,
+                        const uint64_t* slot, uint64_t ntiles, int64_t pe0, int64_t te0,
+                        uint64_t jump, TileEntry* entries, uint64_t* tab, DevResults* res,
                         hipStream_t s);
+uint64_t tile_scan_blocks(uint64_t ntiles);
 void launch_assign(const AssignArgs& a, bool soa, hipStream_t s);
 void launch_cluster(const ClusterArgs& a, bool event_mode, uint64_t grid, hipStream_t s);
+// segment table of a group offset array (see ClusterArgs::seg_lo); needs
+// max_events / q + 2 entries
+void launch_seg_table(const uint32_t* grp_off, const unsigned long long* n_grp_dev,
+                      const unsigned long long* n_ev_dev, const unsigned long long* skip,
+                      uint32_t q, uint64_t max_groups, uint32_t* seg_lo, hipStream_t s);
 // workgroups needed to cover every segment of up to max_events events
 uint64_t cluster_grid(uint64_t max_events, uint32_t q);
 int cluster_capacity();
@@ -77,8 +86,6 @@ void launch_fill_u64(uint64_t* p, uint64_t v, uint64_t n, hipStream_t s);
 // out[0..n] = exclusive prefix of in[0..n), out[n] = total; n = *n_dev if n_dev
 void launch_scan_u32(const uint32_t* in, uint32_t* out, uint64_t n_host,
                      const unsigned long long* n_dev, uint32_t* block_tmp, hipStream_t s);
-void launch_tiles_sorted(const TileRec* recs, uint64_t ntiles, uint64_t carry_last_plus1,
-                         DevResults* res, hipStream_t s);
 void launch_close(const uint64_t* tab, const unsigned long long* n_trig_dev, uint64_t n_win,
                   uint64_t first_open, int flush, uint64_t max_t_plus1_prev, uint64_t tof_max,
                   uint64_t slack, const uint32_t* shot_off, DevResults* res, hipStream_t s);

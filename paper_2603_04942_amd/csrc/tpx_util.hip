@@ -1,4 +1,4 @@
-// Small device utilities of libtpx: fills, prefix sums, the order checks,
+// Small device utilities of libtpx: fills, prefix sums, the close rule,
 // the stable split sort used when events are not in shot order, carry
 // copies between stream chunks, and centroids of externally given labels.
 #include "tpx_kernels.h"
@@ -112,49 +112,6 @@ void launch_scan_u32(const uint32_t* in, uint32_t* out, uint64_t n_host,
     hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kScanBlocks), 0, s, block_tmp);
     hipLaunchKernelGGL(k_scan_down, dim3(kScanBlocks), dim3(kScanThreads), 0, s, in, out, n_host,
                        n_dev, block_tmp);
-}
-
-// ------------------------------------------------------------ order checks
-// Kept events are in shot order when every tile is, and no tile starts below
-// the largest shot of the tiles (and carried events) before it.
-__global__ __launch_bounds__(1024) void k_tiles_sorted(const TileRec* recs, uint64_t ntiles,
-                                                      uint64_t carry_last_plus1, DevResults* res) {
-    __shared__ uint32_t f_s[1024], m_s[1024], ok_s[1024], any_s[1024];
-    const int t = threadIdx.x;
-    const uint64_t per = (ntiles + 1023) / 1024;
-    const uint64_t lo = min<uint64_t>(ntiles, (uint64_t)t * per);
-    const uint64_t hi = min<uint64_t>(ntiles, lo + per);
-    uint32_t first = 0, mx = 0, any = 0, ok = 1;
-    for (uint64_t k = lo; k < hi; ++k) {
-        const TileRec r = recs[k];
-        if (r.n_kept == 0) continue;
-        if (!r.sorted) ok = 0;
-        if (any && r.first_g < mx) ok = 0;
-        if (!any) first = r.first_g;
-        any = 1;
-        mx = max(mx, r.last_g);
-    }
-    f_s[t] = first;
-    m_s[t] = mx;
-    ok_s[t] = ok;
-    any_s[t] = any;
-    __syncthreads();
-    if (t == 0) {
-        bool all_ok = true, have = carry_last_plus1 > 0;
-        uint64_t run = carry_last_plus1 ? carry_last_plus1 - 1 : 0;
-        for (int k = 0; k < 1024; ++k) {
-            if (!any_s[k]) continue;
-            if (!ok_s[k]) all_ok = false;
-            if (have && f_s[k] < run) all_ok = false;
-            have = true;
-            run = max<uint64_t>(run, m_s[k]);
-        }
-        res->unsorted = all_ok ? 0ull : 1ull;
-    }
-}
-void launch_tiles_sorted(const TileRec* recs, uint64_t ntiles, uint64_t carry_last_plus1,
-                         DevResults* res, hipStream_t s) {
-    hipLaunchKernelGGL(k_tiles_sorted, dim3(1), dim3(1024), 0, s, recs, ntiles, carry_last_plus1, res);
 }
 
 // Shots [first_open, s_close) close in this chunk: trigger s+1 was seen and a
