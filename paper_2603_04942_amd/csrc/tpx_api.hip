@@ -350,7 +350,6 @@ tpx_status tpx_cluster(tpx_events ev, size_t n_ev, const tpx_params* p_h, uint32
     a.dxy = p_h->dxy;
     a.dt = p_h->dt_ticks;
     a.labels = labels;
-    a.lb_status = w.lb;
     a.res = w.res;
     a.g_parent = w.big[0];
     a.g_chain = w.big[1];
@@ -358,7 +357,7 @@ tpx_status tpx_cluster(tpx_events ev, size_t n_ev, const tpx_params* p_h, uint32
     a.g_t = w.big[3];
     a.g_sl = w.big[4];
     a.g_xy = w.big[5];
-    launch_seg_table(w.grp_off, a.n_grp_dev, a.n_ev_dev, nullptr, kQ, n_ev, w.seg_lo, s);
+    launch_seg_table(w.grp_off, a.n_grp_dev, a.n_ev_dev, nullptr, kQ, n_ev, w.seg_lo, w.res, s);
     launch_cluster(a, true, cluster_grid(n_ev, kQ), s);
     if ((rc = read_res(w.res, &r, s))) return rc;
     if ((rc = res_error(r))) return rc;
@@ -433,8 +432,7 @@ struct tpx_stream {
     uint32_t *shot_arr, *keys, *vals, *keys2, *vals2, *flags, *scan, *grp_off, *grp_shot;
     uint64_t* ev_sorted;
     uint32_t* block_tmp;
-    uint64_t* lb_seg;
-    uint32_t* seg_lo;
+    uint32_t *seg_lo, *seg_cnt, *seg_off, *rank;
     uint32_t* big[6];
     uint64_t* g_acc;
     // committed host state
@@ -493,7 +491,9 @@ ClusterArgs stream_cluster_args(tpx_stream* s, tpx_hit* hits, uint64_t hit_cap) 
     a.walk = s->p.walk_lut_ns;
     a.hits = hits;
     a.hit_cap = hit_cap;
-    a.lb_status = s->lb_seg;
+    a.rank = s->rank;
+    a.seg_cnt = s->seg_cnt;
+    a.seg_off = s->seg_off;
     a.res = s->res;
     a.g_parent = s->big[0];
     a.g_chain = s->big[1];
@@ -548,7 +548,6 @@ void stream_front(tpx_stream* s, const uint64_t* chunk, uint64_t n, hipStream_t 
                        s->tdc_epoch, s->p.jump_ticks, s->dw.entries, s->tab[s->cur] + s->n_win,
                        s->res, hs);
     launch_fill_u64(s->dw.lb, 0, nt + 1, hs);
-    launch_fill_u64(s->lb_seg, 0, (s->n_carry + n) / kQ + 4, hs);
 }
 
 tpx_status stream_fast(tpx_stream* s, const uint64_t* chunk, uint64_t n, int flush, tpx_hit* hits,
@@ -574,9 +573,12 @@ tpx_status stream_fast(tpx_stream* s, const uint64_t* chunk, uint64_t n, int flu
     c.n_grp_dev = &s->res->n_close_grp;
     c.skip = &s->res->unsorted;
     c.seg_lo = s->seg_lo;
-    launch_seg_table(c.grp_off, c.n_grp_dev, c.n_ev_dev, c.skip, kQ, rows, s->seg_lo, hs);
+    launch_seg_table(c.grp_off, c.n_grp_dev, c.n_ev_dev, c.skip, kQ, rows, s->seg_lo, s->res, hs);
     mark(s, 4, hs);
-    launch_cluster(c, false, cluster_grid(s->n_carry + n, kQ), hs);
+    const uint64_t grid = cluster_grid(s->n_carry + n, kQ);
+    launch_cluster(c, false, grid, hs);
+    launch_scan_u32(s->seg_cnt, s->seg_off, 0, &s->res->n_seg, s->block_tmp, hs);
+    launch_seg_centroid(c, grid, hs);
     mark(s, 5, hs);
     const int nx = 1 - s->cur;
     launch_carry_out(s->ev, nullptr, nullptr, s->shot_off, &s->res->n_groups, &s->res->n_close_ev,
@@ -620,8 +622,11 @@ tpx_status stream_general(tpx_stream* s, const uint64_t* chunk, uint64_t n, int 
     c.n_ev_dev = &s->res->n_close_ev;
     c.n_grp_dev = &s->res->n_close_list;
     c.seg_lo = s->seg_lo;
-    launch_seg_table(c.grp_off, c.n_grp_dev, c.n_ev_dev, nullptr, kQ, N, s->seg_lo, hs);
-    launch_cluster(c, false, cluster_grid(N, kQ), hs);
+    launch_seg_table(c.grp_off, c.n_grp_dev, c.n_ev_dev, nullptr, kQ, N, s->seg_lo, s->res, hs);
+    const uint64_t grid = cluster_grid(N, kQ);
+    launch_cluster(c, false, grid, hs);
+    launch_scan_u32(s->seg_cnt, s->seg_off, 0, &s->res->n_seg, s->block_tmp, hs);
+    launch_seg_centroid(c, grid, hs);
     const int nx = 1 - s->cur;
     launch_carry_out(s->ev_sorted, vo, ko, nullptr, nullptr, &s->res->n_close_ev, &s->res->n_kept,
                      s->c_gidx[s->cur], s->n_carry, s->ev_next, s->c_ev[nx], s->c_shot[nx],
@@ -688,10 +693,12 @@ tpx_status tpx_stream_create(const tpx_params* p_h, size_t max_chunk_pkts, tpx_s
     ALLOC(s->grp_shot, s->ev_cap + 1);
     ALLOC(s->ev_sorted, s->ev_cap);
     ALLOC(s->block_tmp, 1024);
-    ALLOC(s->lb_seg, s->seg_cap);
     ALLOC(s->seg_lo, s->seg_cap);
+    ALLOC(s->seg_cnt, s->seg_cap);
+    ALLOC(s->seg_off, s->seg_cap + 1);
+    ALLOC(s->rank, s->ev_cap);
     for (int k = 0; k < 6; ++k) ALLOC(s->big[k], s->ev_cap);
-    ALLOC(s->g_acc, 6 * s->ev_cap);
+    ALLOC(s->g_acc, 8 * s->ev_cap);
 #undef ALLOC
     s->pix_epoch = p_h->pix_epoch0;
     s->tdc_epoch = p_h->tdc_epoch0;

@@ -2,49 +2,47 @@
 // Eqs. 3-5, closed transitively; Centroiding, Eqs. 8-9).
 //
 // Events arrive grouped by shot.  Groups are packed into segments of about
-// `q` events and every workgroup clusters one segment.  Workgroups take their
-// segment from an atomic ticket, so that segment k's workgroup started after
-// those of segments 0..k-1; a decoupled look-back over segments then gives
-// each segment its first output slot.  Inside a segment:
-//   1. every event is dropped into a hashed 256x64 image of its pixel address
-//      (LDS); events sharing an image slot are chained behind the slot owner;
-//   2. each event visits the slots of its forward neighbourhood (the half of
-//      the (2r+1)^2 box that comes after it, plus its own slot) and unites
-//      with every chained event that has the same shot, |dx|,|dy| <= r and
-//      |dt| <= r_t: the edges of the paper's Hadamard adjacency A;
-//   3. a lock-free union-find in LDS, always hooking the larger root under the
-//      smaller, leaves every component rooted at its smallest event position,
-//      which is also its smallest event index;
-//   4. ToT-weighted integer moments are accumulated per root with LDS atomics
-//      (exact, so the result does not depend on the order of the atomics) and
-//      each root emits one hit: X = sum(ToT x)/sum(ToT), same for Y and ToF.
-// Segments larger than the LDS capacity take the same steps with their
-// per-event arrays in global memory.  Control flow around every barrier is
-// uniform: one segment per workgroup, a fixed sequence of phases.
+// `q` events (the groups whose first event lies in [k q, (k+1) q)); the
+// segment table comes from k_seg_table.
+//
+// k_cluster, one workgroup per segment, finds the components of the
+// neighbourhood graph (same shot, |dx|, |dy| <= r, |dt| <= r_t: the edges of
+// the paper's Hadamard adjacency A) in four steps over LDS:
+//   1. every event is dropped into a hashed 256x64 image of its pixel address;
+//      events sharing an image slot are chained behind the slot owner;
+//   2. every event points at the smallest event among itself and its
+//      neighbours (a plain store: no atomics), which makes a forest whose
+//      roots are local minima;
+//   3. after path compression, each edge of the forward half-neighbourhood
+//      whose ends lie in different trees is united (lock-free union-find that
+//      hooks the larger root under the smaller); most edges are already
+//      inside one tree;
+//   4. a final find gives each event its root = the smallest event position
+//      of its component = its label.
+// In event mode (tpx_cluster) the kernel writes labels.  In stream mode it
+// writes, for every event, the rank of its component within the segment
+// (components ordered by label) and the segment's component count; after a
+// prefix sum over segments, k_seg_centroid accumulates exact integer moments
+// per component and writes one hit per component at its final position, so no
+// segment ever waits for another.  Segments larger than the LDS capacity take
+// the same steps with their per-event arrays in global memory.
 #include "tpx_kernels.h"
 
 namespace tpx {
 
 constexpr int kCap = 2048;             // events per segment held in LDS
-constexpr int kWG = 512;               // threads per workgroup
-constexpr int kK = kCap / kWG;         // events per thread
+constexpr int kWG = 512;               // threads per workgroup (k_cluster)
 constexpr int kH = 16384;              // image slots: (y & 63) << 8 | x
 constexpr uint32_t kNone32 = 0xFFFFFFFFu;
 constexpr uint32_t kNone16 = 0xFFFFu;
 
-// LDS byte layout of the small-segment path
-constexpr int kOffImg = 0;             // u16[kH]
+// LDS byte layout of k_cluster's small-segment path
+constexpr int kOffImg = 0;             // u16[kH] slot owner
 constexpr int kOffPar = 32768;         // u32[kCap] union-find parent
-constexpr int kOffChn = 40960;         // u32[kCap] first chained event of a slot owner
-constexpr int kOffT = 49152;           // u32[kCap] time (ticks after the shot reference)
-constexpr int kOffSl = 57344;          // u32[kCap] group (shot) of the event
-constexpr int kOffXy = 65536;          // u16[kCap] x | y << 8
-constexpr int kOffNxt = 69632;         // u16[kCap] next chained event
-constexpr int kLdsMain = 73728;
-// accumulators overlaid on the same bytes once the components are known
-constexpr int kOffW = 0, kOffSx = 8192, kOffSy = 16384, kOffCnt = 24576, kOffTmin = 32768,
-              kOffSt = 40960;  // u64[kCap]
-static_assert(kOffSt + 8 * kCap <= kLdsMain, "accumulator overlay");
+constexpr int kOffEv = 40960;          // u64[kCap] x | y << 8 | group start << 16 | t << 32
+constexpr int kOffChn = 57344;         // u32[kCap] first chained event of a slot owner
+constexpr int kOffNxt = 65536;         // u16[kCap] next chained event
+constexpr int kLdsMain = 69632;
 static_assert(4 * kH <= kLdsMain, "big-path image");
 
 __device__ inline uint32_t slot_of(uint32_t x, uint32_t y) { return ((y & 63u) << 8) | x; }
@@ -105,11 +103,6 @@ __device__ inline void uf_unite(uint32_t* par, uint32_t a, uint32_t b, uint32_t 
     }
 }
 
-struct Ev {
-    uint32_t x, y, tot, t, g;
-    uint64_t pos;  // position in the sorted event order
-};
-
 // group (shot) of sorted position p: last g in [lo, hi) with off[g] <= p
 template <typename P>
 __device__ inline uint32_t group_of(P off, uint32_t lo, uint32_t hi, uint32_t p) {
@@ -120,27 +113,50 @@ __device__ inline uint32_t group_of(P off, uint32_t lo, uint32_t hi, uint32_t p)
     return lo;
 }
 
+// Segment k: groups [g_lo, g_hi), events [e0, e0 + n).  False (and the
+// internal-error flag) when the tables are inconsistent.
+struct Seg {
+    uint32_t g_lo, g_hi, n;
+    uint64_t e0;
+};
+__device__ inline bool seg_bounds(const ClusterArgs& a, uint32_t k, uint64_t N, Seg& s) {
+    s.g_lo = a.seg_lo[k];
+    s.g_hi = a.seg_lo[k + 1];
+    s.e0 = a.grp_off[s.g_lo];
+    const uint64_t e1 = a.grp_off[s.g_hi];
+    if (s.g_hi < s.g_lo || e1 < s.e0 || e1 > N) {
+        if (threadIdx.x == 0) atomicOr(&a.res->err, (unsigned long long)kErrInternal);
+        return false;
+    }
+    s.n = (uint32_t)(e1 - s.e0);
+    return true;
+}
+
+__device__ inline uint64_t n_events(const ClusterArgs& a) {
+    return (a.skip && *a.skip) ? 0 : *a.n_ev_dev;
+}
+
+// Pixel address, time and the first position of its group (relative to the
+// segment start), for the event at sorted position p of group g.
+struct Ev {
+    uint32_t x, y, t, gs;
+};
+
 template <bool kEvent>
-__device__ inline bool load_event(const ClusterArgs& a, uint64_t p, const uint32_t* goff, uint32_t goff_base,
-                                  uint32_t ng, bool goff_lds, uint32_t g_lo, Ev& e,
-                                  unsigned long long* err) {
-    e.pos = p;
-    const uint32_t g = goff_lds ? g_lo + group_of(goff, 0, ng, (uint32_t)p)
-                                : group_of(a.grp_off, g_lo, g_lo + ng, (uint32_t)p);
-    (void)goff_base;
-    e.g = g;
+__device__ inline Ev load_event(const ClusterArgs& a, uint64_t p, uint32_t g, uint64_t e0,
+                                unsigned long long* err) {
+    Ev e;
+    const uint64_t first = a.grp_off[g];
+    e.gs = (uint32_t)(first - e0);
     if constexpr (!kEvent) {
         const uint64_t pk = a.ev[p];
         e.x = ev_x(pk);
         e.y = ev_y(pk);
-        e.tot = ev_tot(pk);
         e.t = ev_t(pk);
     } else {
         const uint64_t o = a.perm ? a.perm[p] : p;
         e.x = a.soa.x[o];
         e.y = a.soa.y[o];
-        e.tot = 0;
-        const uint64_t first = a.grp_off[g];
         const uint64_t of = a.perm ? a.perm[first] : first;
         const uint64_t d = a.soa.toa[o] - a.soa.toa[of] + (1ull << 31);
         if (e.x > 255u || e.y > 255u || d >= (1ull << 32)) {
@@ -150,7 +166,11 @@ __device__ inline bool load_event(const ClusterArgs& a, uint64_t p, const uint32
         }
         e.t = (uint32_t)d;
     }
-    return true;
+    return e;
+}
+
+__device__ inline uint64_t pack_lds(const Ev& e) {
+    return (uint64_t)e.x | ((uint64_t)e.y << 8) | ((uint64_t)e.gs << 16) | ((uint64_t)e.t << 32);
 }
 
 // global event index of sorted position p (stream path)
@@ -163,6 +183,353 @@ __device__ inline uint64_t orig_of(const ClusterArgs& a, uint64_t p) {
     return a.perm ? a.perm[p] : p;
 }
 
+// Calls f(j) for every event j in image slot (nx, ny): the owner, then its
+// chain.  Returns false when a chain is longer than the segment.
+template <typename F>
+__device__ inline bool slot_events(const uint16_t* img, const uint32_t* chn, const uint16_t* nxt,
+                                   int nx, int ny, uint32_t n, F&& f) {
+    const uint32_t w = img[slot_of((uint32_t)nx, (uint32_t)ny)];
+    if (w == kNone16) return true;
+    f(w);
+    uint32_t j = chn[w];
+    uint32_t steps = 0;
+    while (j != kNone32) {
+        f(j);
+        if (++steps > n) return false;
+        const uint32_t nn = nxt[j];
+        j = nn == kNone16 ? kNone32 : nn;
+    }
+    return true;
+}
+
+// Calls f(j, fwd) for every event j != i in the image slots of the
+// (2r+1)^2 box around (x, y); fwd marks the forward half (later rows, later
+// columns of the same row, and smaller positions in the event's own slot),
+// which holds every undirected edge exactly once.  R > 0 fixes the radius at
+// compile time (unrolled); R == 0 takes it from r_rt.
+template <int R, typename F>
+__device__ inline bool box_events(const uint16_t* img, const uint32_t* chn, const uint16_t* nxt,
+                                  uint32_t i, int x, int y, int r_rt, uint32_t n, F&& f) {
+    bool ok = true;
+    auto one = [&](int dx, int dy) {
+        const int nx = x + dx, ny = y + dy;
+        if (nx < 0 || nx > 255 || ny < 0 || ny > 255) return;
+        const bool fwd_slot = dy > 0 || (dy == 0 && dx > 0);
+        const bool own = dx == 0 && dy == 0;
+        ok &= slot_events(img, chn, nxt, nx, ny, n, [&](uint32_t j) {
+            if (j != i) f(j, fwd_slot || (own && j < i));
+        });
+    };
+    if constexpr (R > 0) {
+#pragma unroll
+        for (int dy = -R; dy <= R; ++dy)
+#pragma unroll
+            for (int dx = -R; dx <= R; ++dx) one(dx, dy);
+    } else {
+        for (int dy = -r_rt; dy <= r_rt; ++dy)
+            for (int dx = -r_rt; dx <= r_rt; ++dx) one(dx, dy);
+    }
+    return ok;
+}
+
+__device__ inline bool is_edge(uint64_t me, uint64_t o, int r, uint32_t dt) {
+    const uint32_t ya = (uint32_t)(me >> 8) & 255u, yb = (uint32_t)(o >> 8) & 255u;
+    const uint32_t xa = (uint32_t)me & 255u, xb = (uint32_t)o & 255u;
+    return ((me ^ o) & 0xFFFF0000ull) == 0 &&                           // same group
+           absdiff((uint32_t)(me >> 32), (uint32_t)(o >> 32)) <= dt &&  // |dt|
+           absdiff(ya, yb) <= (uint32_t)r && absdiff(xa, xb) <= (uint32_t)r;
+}
+
+// ------------------------------------------------------------ LDS segment
+// Every phase walks the events i = tid + q kWG, q < kK; per-event state lives
+// in LDS between phases.
+template <bool kEvent, int R>
+__device__ void seg_small(const ClusterArgs& a, uint8_t* lds, uint32_t* scan_tmp,
+                          const uint32_t* goff, bool goff_lds, const Seg& sg, uint32_t k) {
+    uint16_t* img = (uint16_t*)(lds + kOffImg);
+    uint32_t* par = (uint32_t*)(lds + kOffPar);
+    uint64_t* evs = (uint64_t*)(lds + kOffEv);
+    uint32_t* chn = (uint32_t*)(lds + kOffChn);
+    uint16_t* nxt = (uint16_t*)(lds + kOffNxt);
+    const int tid = threadIdx.x;
+    const int r = (int)a.dxy;
+    const uint32_t dt = a.dt, n = sg.n;
+    const uint64_t e0 = sg.e0;
+    unsigned long long* err = &a.res->err;
+
+    {
+        uint4* v = (uint4*)img;
+        for (int i = tid; i < kH * 2 / 16; i += kWG) v[i] = make_uint4(~0u, ~0u, ~0u, ~0u);
+    }
+    for (uint32_t i = tid; i < n; i += kWG) {
+        const uint32_t p = (uint32_t)(e0 + i);
+        const uint32_t g = goff_lds ? sg.g_lo + group_of(goff, 0, sg.g_hi - sg.g_lo, p)
+                                    : group_of(a.grp_off, sg.g_lo, sg.g_hi, p);
+        evs[i] = pack_lds(load_event<kEvent>(a, e0 + i, g, e0, err));
+        chn[i] = kNone32;
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < n; i += kWG) {
+        const uint64_t v = evs[i];
+        img[slot_of((uint32_t)v & 255u, (uint32_t)(v >> 8) & 255u)] = (uint16_t)i;
+    }
+    __syncthreads();
+    // events that lost the race for their slot chain behind the owner
+    for (uint32_t i = tid; i < n; i += kWG) {
+        const uint64_t v = evs[i];
+        const uint32_t w = img[slot_of((uint32_t)v & 255u, (uint32_t)(v >> 8) & 255u)];
+        if (w != i) {
+            const uint32_t old = atomicExch(&chn[w], i);
+            nxt[i] = (uint16_t)(old == kNone32 ? kNone16 : old);
+        }
+    }
+    __syncthreads();
+    // every event points at the smallest of itself and its neighbours
+    bool ok = true;
+    for (uint32_t i = tid; i < n; i += kWG) {
+        uint32_t m = i;
+        const uint64_t v = evs[i];
+        ok &= box_events<R>(img, chn, nxt, i, (int)(v & 255u), (int)((v >> 8) & 255u), r, n,
+                            [&](uint32_t j, bool) {
+                                if (j < m && is_edge(v, evs[j], r, dt)) m = j;
+                            });
+        par[i] = m;
+    }
+    __syncthreads();
+    // path compression: every event points at the root of its tree (a
+    // concurrent reader sees the old parent or the root, both ancestors)
+    for (uint32_t i = tid; i < n; i += kWG) {
+        uint32_t p = ald(par + i), steps = 0;
+        for (uint32_t nx; p != (nx = ald(par + p)) && ++steps <= n;) p = nx;
+        ast(par + i, p);
+    }
+    __syncthreads();
+    // edges between different trees
+    for (uint32_t i = tid; i < n; i += kWG) {
+        const uint64_t v = evs[i];
+        ok &= box_events<R>(img, chn, nxt, i, (int)(v & 255u), (int)((v >> 8) & 255u), r, n,
+                            [&](uint32_t j, bool fwd) {
+                                if (fwd && ald(par + j) != ald(par + i) && is_edge(v, evs[j], r, dt))
+                                    uf_unite(par, i, j, n, err);
+                            });
+    }
+    if (!ok) atomicOr(err, (unsigned long long)kErrLoopChain);
+    __syncthreads();
+    // final roots, stored as parents
+    for (uint32_t i = tid; i < n; i += kWG) ast(par + i, uf_find(par, i, n, err));
+    __syncthreads();
+
+    if constexpr (kEvent) {
+        uint32_t nroot = 0;
+        for (uint32_t i = tid; i < n; i += kWG) {
+            const uint32_t rt = par[i];
+            a.labels[orig_of(a, e0 + i)] = (uint32_t)orig_of(a, e0 + rt);
+            nroot += rt == i;
+        }
+        for (int d = 32; d > 0; d >>= 1) nroot += __shfl_xor(nroot, d, 64);
+        if (__lane_id() == 0 && nroot) atomicAdd(&a.res->n_hits, (unsigned long long)nroot);
+    } else {
+        // rank of every component (in label order) within the segment, kept
+        // at the root's chain slot (chains are no longer needed)
+        uint32_t running = 0;
+        const uint32_t rounds = (n + kWG - 1) / kWG;
+        for (uint32_t rd = 0; rd < rounds; ++rd) {
+            const uint32_t i = rd * kWG + tid;
+            uint32_t tot;
+            const bool is_root = i < n && par[i] == i;
+            const uint32_t rk = running + wg_flag_scan<kWG>(is_root, scan_tmp, &tot);
+            if (is_root) chn[i] = rk;
+            running += tot;
+        }
+        __syncthreads();
+        for (uint32_t i = tid; i < n; i += kWG) a.rank[e0 + i] = chn[par[i]];
+        if (tid == 0) a.seg_cnt[k] = running;
+    }
+}
+
+// ------------------------------------------------------ global-memory segment
+template <bool kEvent>
+__device__ void seg_big(const ClusterArgs& a, uint8_t* lds, uint32_t* scan_tmp, const Seg& sg,
+                        uint32_t k) {
+    uint32_t* img = (uint32_t*)lds;  // u32[kH], all-ones = empty
+    const uint64_t e0 = sg.e0;
+    const uint32_t n = sg.n;
+    uint32_t* par = a.g_parent + e0;
+    uint32_t* chn = a.g_chain + e0;
+    uint32_t* nxt = a.g_next + e0;
+    uint32_t* tt = a.g_t + e0;
+    uint32_t* gs = a.g_sl + e0;
+    uint32_t* xy = a.g_xy + e0;
+    const int tid = threadIdx.x;
+    const int r = (int)a.dxy;
+    const uint32_t dt = a.dt;
+    unsigned long long* err = &a.res->err;
+    if (tid == 0) atomicAdd(&a.res->big_segments, 1ull);
+    {
+        uint4* v = (uint4*)img;
+        for (int i = tid; i < kH * 4 / 16; i += kWG) v[i] = make_uint4(~0u, ~0u, ~0u, ~0u);
+    }
+    for (uint32_t i = tid; i < n; i += kWG) {
+        const uint32_t g = group_of(a.grp_off, sg.g_lo, sg.g_hi, (uint32_t)(e0 + i));
+        const Ev e = load_event<kEvent>(a, e0 + i, g, e0, err);
+        par[i] = i;
+        chn[i] = kNone32;
+        tt[i] = e.t;
+        gs[i] = e.gs;
+        xy[i] = e.x | (e.y << 8);
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < n; i += kWG) {
+        const uint32_t v = xy[i];
+        img[slot_of(v & 255u, (v >> 8) & 255u)] = i;
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < n; i += kWG) {
+        const uint32_t v = xy[i];
+        const uint32_t w = img[slot_of(v & 255u, (v >> 8) & 255u)];
+        if (w != i) nxt[i] = atomicExch(&chn[w], i);
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < n; i += kWG) {
+        const uint32_t v = xy[i];
+        const int x = (int)(v & 255u), y = (int)((v >> 8) & 255u);
+        const uint32_t t = tt[i], g = gs[i];
+        for (int dy = 0; dy <= r; ++dy) {
+            const int ny = y + dy;
+            if (ny > 255) break;
+            for (int dx = (dy == 0 ? 0 : -r); dx <= r; ++dx) {
+                const int nx = x + dx;
+                if (nx < 0 || nx > 255) continue;
+                const bool own = dx == 0 && dy == 0;
+                const uint32_t w = img[slot_of((uint32_t)nx, (uint32_t)ny)];
+                uint32_t j = w;
+                uint32_t steps = 0;
+                while (j != kNone32) {
+                    if (j != i && (!own || j < i)) {
+                        const uint32_t vj = xy[j];
+                        if (gs[j] == g && absdiff(tt[j], t) <= dt &&
+                            abs((int)(vj & 255u) - x) <= r && abs((int)((vj >> 8) & 255u) - y) <= r)
+                            uf_unite(par, i, j, n, err);
+                    }
+                    if (++steps > n) {
+                        atomicOr(err, (unsigned long long)kErrLoopChain);
+                        break;
+                    }
+                    j = (j == w) ? chn[j] : nxt[j];
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < n; i += kWG) chn[i] = uf_find(par, i, n, err);  // root
+    __syncthreads();
+    if constexpr (kEvent) {
+        uint32_t nroot = 0;
+        for (uint32_t i = tid; i < n; i += kWG) {
+            const uint32_t rt = chn[i];
+            a.labels[orig_of(a, e0 + i)] = (uint32_t)orig_of(a, e0 + rt);
+            nroot += rt == i;
+        }
+        for (int d = 32; d > 0; d >>= 1) nroot += __shfl_xor(nroot, d, 64);
+        if (__lane_id() == 0 && nroot) atomicAdd(&a.res->n_hits, (unsigned long long)nroot);
+    } else {
+        // ranks of the roots in position order, one workgroup-wide round at a time
+        uint32_t running = 0;
+        const uint32_t rounds = (n + kWG - 1) / kWG;
+        for (uint32_t rd = 0; rd < rounds; ++rd) {
+            const uint32_t i = rd * kWG + tid;
+            uint32_t tot;
+            const bool is_root = i < n && chn[i] == i;
+            const uint32_t rk = running + wg_flag_scan<kWG>(is_root, scan_tmp, &tot);
+            if (is_root) par[i] = rk;  // parents are no longer needed: keep the rank
+            running += tot;
+        }
+        __syncthreads();
+        for (uint32_t i = tid; i < n; i += kWG) a.rank[e0 + i] = par[chn[i]];
+        if (tid == 0) a.seg_cnt[k] = running;
+    }
+}
+
+// Segment table: seg_lo[k] = first group whose first event is at or after
+// k q, for k = 0..n_seg (n_seg = ceil(N / q)).  One thread per group g = 0..G
+// fills the k in (grp_off[g-1] / q, grp_off[g] / q]; g = G closes at n_seg.
+__global__ void k_seg_table(const uint32_t* __restrict__ grp_off, const unsigned long long* n_grp_dev,
+                            const unsigned long long* n_ev_dev, const unsigned long long* skip,
+                            uint32_t q, uint32_t* seg_lo, DevResults* res) {
+    const bool sk = skip && *skip;
+    const uint64_t G = *n_grp_dev, N = sk ? 0 : *n_ev_dev;
+    const uint64_t n_seg = (N + q - 1) / q;
+    if (blockIdx.x == 0 && threadIdx.x == 0) res->n_seg = n_seg;
+    if (sk) return;
+    for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g <= G;
+         g += (uint64_t)gridDim.x * blockDim.x) {
+        // offsets never exceed N in a valid table; the clamps keep every
+        // write inside seg_lo[0..n_seg] whatever the table holds
+        const int64_t k_prev = g == 0 ? -1 : (int64_t)min<uint64_t>(grp_off[g - 1] / q, n_seg);
+        const int64_t k_hi = g == G ? (int64_t)n_seg : (int64_t)min<uint64_t>(grp_off[g] / q, n_seg);
+        for (int64_t k = k_prev + 1; k <= k_hi; ++k) seg_lo[k] = (uint32_t)g;
+    }
+}
+
+void launch_seg_table(const uint32_t* grp_off, const unsigned long long* n_grp_dev,
+                      const unsigned long long* n_ev_dev, const unsigned long long* skip,
+                      uint32_t q, uint64_t max_groups, uint32_t* seg_lo, DevResults* res,
+                      hipStream_t s) {
+    uint64_t blocks = (max_groups + 1 + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_seg_table, dim3((unsigned)blocks), dim3(256), 0, s, grp_off, n_grp_dev,
+                       n_ev_dev, skip, q, seg_lo, res);
+}
+
+// One workgroup per segment; the grid covers the largest possible number of
+// segments and workgroups beyond the actual count return at once.
+template <bool kEvent, int R>
+__global__ __launch_bounds__(kWG, 2) void k_cluster(ClusterArgs a) {
+    __shared__ __attribute__((aligned(16))) uint8_t lds[kLdsMain];
+    __shared__ uint32_t scan_tmp[kWG / 64 + 1];
+    __shared__ uint32_t goff[kWG + 1];
+    const int tid = threadIdx.x;
+    const uint32_t k = blockIdx.x;
+    const uint64_t N = n_events(a);
+    const uint64_t n_seg = (N + a.q - 1) / a.q;
+    if (k >= n_seg) return;
+    Seg sg;
+    if (!seg_bounds(a, k, N, sg)) return;
+    if (sg.n == 0) {
+        if (!kEvent && tid == 0) a.seg_cnt[k] = 0;
+        return;
+    }
+    const uint32_t ng = sg.g_hi - sg.g_lo;
+    if (sg.n <= (uint32_t)kCap) {
+        const bool goff_lds = ng <= (uint32_t)kWG;
+        if (goff_lds) {
+            for (uint32_t i = tid; i <= ng; i += kWG) goff[i] = a.grp_off[sg.g_lo + i];
+        }
+        __syncthreads();
+        seg_small<kEvent, R>(a, lds, scan_tmp, goff, goff_lds, sg, k);
+    } else {
+        seg_big<kEvent>(a, lds, scan_tmp, sg, k);
+    }
+    if (tid == 0) atomicMax(&a.res->max_segment, (unsigned long long)sg.n);
+}
+
+uint64_t cluster_grid(uint64_t max_events, uint32_t q) { return max_events / q + 2; }
+
+void launch_cluster(const ClusterArgs& a, bool event_mode, uint64_t grid, hipStream_t s) {
+    if (grid == 0) return;
+    const bool r1 = a.dxy == 1;
+    if (event_mode) {
+        if (r1) hipLaunchKernelGGL((k_cluster<true, 1>), dim3((unsigned)grid), dim3(kWG), 0, s, a);
+        else hipLaunchKernelGGL((k_cluster<true, 0>), dim3((unsigned)grid), dim3(kWG), 0, s, a);
+    } else {
+        if (r1) hipLaunchKernelGGL((k_cluster<false, 1>), dim3((unsigned)grid), dim3(kWG), 0, s, a);
+        else hipLaunchKernelGGL((k_cluster<false, 0>), dim3((unsigned)grid), dim3(kWG), 0, s, a);
+    }
+}
+
+int cluster_capacity() { return kCap; }
+
+// ------------------------------------------------------------- centroids
 // St term of one pixel: ticks (no walk table) or 2^-16 ns fixed point
 __device__ inline uint64_t time_term(const ClusterArgs& a, uint32_t tot, uint32_t t) {
     if (a.walk) {
@@ -199,430 +566,147 @@ __device__ inline void write_hit(const ClusterArgs& a, uint64_t h, uint32_t g, u
     a.hits[h] = o;
 }
 
-// Look-back over segments by the 64 lanes of wave 0; returns this segment's
-// first output slot.
-__device__ inline uint64_t seg_lookback(const ClusterArgs& a, uint64_t ticket, uint32_t count) {
-    uint64_t p = 0;
-    if (ticket > 0) {
-        if (__lane_id() == 0) lb_publish(a.lb_status, ticket, kLbAggregate, count);
-        p = lb_lookback_wave<LbSum>(a.lb_status, ticket, &a.res->err);
-    }
-    if (__lane_id() == 0) lb_publish(a.lb_status, ticket, kLbInclusive, p + count);
-    return p;
-}
+constexpr int kCWG = 256;      // threads per workgroup (k_seg_centroid)
+constexpr int kHitCap = 1024;  // components per segment accumulated in LDS
 
-// Visit every chained event of image slot (nx, ny) that is a neighbour of
-// event i (same shot, |dx|, |dy| <= r, |dt| <= dt) and unite with it.  On the
-// event's own slot only smaller positions are taken, so each pair is seen once.
-template <typename IMG, typename NXT, typename XY>
-__device__ inline void visit_slot(IMG img, uint32_t* chn, NXT nxt, const uint32_t* tt,
-                                  const uint32_t* sl, XY xy, uint32_t* par, uint32_t i, int x, int y, uint32_t t, uint32_t g,
-                                  int nx, int ny, bool own, int r, uint32_t dt, uint32_t n,
-                                  uint32_t empty, unsigned long long* err) {
-    const uint32_t w = img[slot_of((uint32_t)nx, (uint32_t)ny)];
-    if (w == empty) return;
-    uint32_t j = w;
-    uint32_t link = chn[w];
-    uint32_t steps = 0;
-    while (true) {
-        if (j != i && (!own || j < i)) {
-            const uint32_t v = xy[j];
-            const int xj = (int)(v & 255u), yj = (int)((v >> 8) & 255u);
-            if (sl[j] == g && absdiff(tt[j], t) <= dt && abs(xj - x) <= r && abs(yj - y) <= r)
-                uf_unite(par, i, j, n, err);
-        }
-        if (link == kNone32) break;
-        if (++steps > n) {
-            atomicOr(err, (unsigned long long)kErrLoopChain);
-            break;
-        }
-        j = link;
-        const uint32_t nn = nxt[j];
-        link = (nn == empty) ? kNone32 : nn;
-    }
-}
-
-// ------------------------------------------------------------ LDS segment
-template <bool kEvent>
-__device__ void seg_small(const ClusterArgs& a, uint8_t* lds, uint32_t* scan_tmp, uint64_t* bc,
-                          const uint32_t* goff, bool goff_lds, uint32_t g_lo, uint32_t ng,
-                          uint64_t e0, uint32_t n, uint64_t ticket) {
-    uint16_t* img = (uint16_t*)(lds + kOffImg);
-    uint32_t* par = (uint32_t*)(lds + kOffPar);
-    uint32_t* chn = (uint32_t*)(lds + kOffChn);
-    uint32_t* tt = (uint32_t*)(lds + kOffT);
-    uint32_t* sl = (uint32_t*)(lds + kOffSl);
-    uint16_t* xy = (uint16_t*)(lds + kOffXy);
-    uint16_t* nxt = (uint16_t*)(lds + kOffNxt);
+// One workgroup per segment: exact integer moments of every component (LDS
+// atomics, so the result does not depend on their order), then one hit per
+// component at seg_off[k] + rank: X = sum(ToT x) / sum(ToT), same for Y and
+// ToF; plain means when a component has no ToT at all.
+__global__ __launch_bounds__(kCWG) void k_seg_centroid(ClusterArgs a) {
+    __shared__ uint32_t W[kHitCap], SX[kHitCap], SY[kHitCap], CNT[kHitCap], TMIN[kHitCap],
+        MINP[kHitCap];
+    __shared__ unsigned long long ST[kHitCap];
+    __shared__ uint32_t goff[kCWG + 1];
     const int tid = threadIdx.x;
-    const int r = (int)a.dxy;
-    const uint32_t dt = a.dt;
-    unsigned long long* err = &a.res->err;
-
-    // image of empty slots
-    {
-        uint4* v = (uint4*)img;
-        for (int i = tid; i < kH * 2 / 16; i += kWG) v[i] = make_uint4(~0u, ~0u, ~0u, ~0u);
+    const uint32_t k = blockIdx.x;
+    const uint64_t N = n_events(a);
+    const uint64_t n_seg = (N + a.q - 1) / a.q;
+    if (k == 0 && tid == 0) a.res->n_hits = a.seg_off[n_seg];
+    if (k >= n_seg) return;
+    Seg sg;
+    if (!seg_bounds(a, k, N, sg)) return;
+    const uint32_t cnt = a.seg_cnt[k], n = sg.n;
+    if (cnt == 0) return;
+    const uint64_t e0 = sg.e0, out0 = a.seg_off[k];
+    const uint32_t ng = sg.g_hi - sg.g_lo;
+    const bool goff_lds = ng <= (uint32_t)kCWG;
+    if (goff_lds) {
+        for (uint32_t i = tid; i <= ng; i += kCWG) goff[i] = a.grp_off[sg.g_lo + i];
     }
-    Ev ev[kK];
-    uint32_t root[kK];
-#pragma unroll
-    for (int k = 0; k < kK; ++k) {
-        const uint32_t i = tid + k * kWG;
-        if (i < n) {
-            load_event<kEvent>(a, e0 + i, goff, 0, ng, goff_lds, g_lo, ev[k], err);
-            par[i] = i;
-            chn[i] = kNone32;
-            tt[i] = ev[k].t;
-            sl[i] = ev[k].g;
-            xy[i] = (uint16_t)(ev[k].x | (ev[k].y << 8));
-        }
+    if (cnt > n) {
+        if (tid == 0) atomicOr(&a.res->err, (unsigned long long)kErrInternal);
+        return;
     }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < kK; ++k) {
-        const uint32_t i = tid + k * kWG;
-        if (i < n) img[slot_of(ev[k].x, ev[k].y)] = (uint16_t)i;
-    }
-    __syncthreads();
-    // events that lost the race for their slot chain behind the owner
-#pragma unroll
-    for (int k = 0; k < kK; ++k) {
-        const uint32_t i = tid + k * kWG;
-        if (i < n) {
-            const uint32_t w = img[slot_of(ev[k].x, ev[k].y)];
-            if (w != i) {
-                const uint32_t old = atomicExch(&chn[w], i);
-                nxt[i] = (uint16_t)(old == kNone32 ? kNone16 : old);
-            }
-        }
-    }
-    __syncthreads();
-    // edges of the neighbourhood graph
-#pragma unroll
-    for (int k = 0; k < kK; ++k) {
-        const uint32_t i = tid + k * kWG;
-        if (i < n) {
-            const int x = (int)ev[k].x, y = (int)ev[k].y;
-            for (int dy = 0; dy <= r; ++dy) {
-                const int ny = y + dy;
-                if (ny > 255) break;
-                for (int dx = (dy == 0 ? 0 : -r); dx <= r; ++dx) {
-                    const int nx = x + dx;
-                    if (nx < 0 || nx > 255) continue;
-                    visit_slot(img, chn, nxt, tt, sl, xy, par, i, x, y,
-                               ev[k].t, ev[k].g, nx, ny, dx == 0 && dy == 0, r, dt, n, kNone16,
-                               err);
-                }
-            }
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < kK; ++k) {
-        const uint32_t i = tid + k * kWG;
-        root[k] = i < n ? uf_find(par, i, n, err) : 0u;
-    }
-    __syncthreads();
-
-    if constexpr (kEvent) {
-        uint32_t nroot = 0;
-#pragma unroll
-        for (int k = 0; k < kK; ++k) {
-            const uint32_t i = tid + k * kWG;
-            if (i < n) {
-                a.labels[orig_of(a, e0 + i)] = (uint32_t)orig_of(a, e0 + root[k]);
-                nroot += root[k] == i;
-            }
-        }
-        for (int d = 32; d > 0; d >>= 1) nroot += __shfl_xor(nroot, d, 64);
-        if (__lane_id() == 0 && nroot) atomicAdd(&a.res->n_hits, (unsigned long long)nroot);
-    } else {
-        uint32_t* W = (uint32_t*)(lds + kOffW);
-        uint32_t* SX = (uint32_t*)(lds + kOffSx);
-        uint32_t* SY = (uint32_t*)(lds + kOffSy);
-        uint32_t* CNT = (uint32_t*)(lds + kOffCnt);
-        uint32_t* TMIN = (uint32_t*)(lds + kOffTmin);
-        unsigned long long* ST = (unsigned long long*)(lds + kOffSt);
-        for (uint32_t i = tid; i < n; i += kWG) {
-            W[i] = 0;
-            SX[i] = 0;
-            SY[i] = 0;
-            CNT[i] = 0;
-            TMIN[i] = kNone32;
-            ST[i] = 0;
+    if (cnt > (uint32_t)kHitCap) {
+        // more components than LDS holds: 8 global words per component, in the
+        // segment's own range of the scratch
+        unsigned long long* acc = (unsigned long long*)a.g_acc + 8 * e0;
+        for (uint32_t c = tid; c < cnt; c += kCWG) {
+            unsigned long long* q = acc + 8 * c;
+            q[0] = 0;
+            q[1] = 0;
+            q[2] = 0;
+            q[3] = 0;
+            q[4] = 0;
+            q[5] = ~0ull;  // min t
+            q[6] = ~0ull;  // min position
         }
         __syncthreads();
-#pragma unroll
-        for (int k = 0; k < kK; ++k) {
-            const uint32_t i = tid + k * kWG;
-            if (i < n) {
-                const uint32_t rr = root[k];
-                const Ev& e = ev[k];
-                atomicAdd(&W[rr], e.tot);
-                atomicAdd(&SX[rr], e.tot * e.x);
-                atomicAdd(&SY[rr], e.tot * e.y);
-                atomicAdd(&CNT[rr], 1u);
-                atomicMin(&TMIN[rr], e.t);
-                atomicAdd(&ST[rr], (unsigned long long)time_term(a, e.tot, e.t));
+        for (uint32_t i = tid; i < n; i += kCWG) {
+            const uint64_t pk = a.ev[e0 + i];
+            const uint32_t rk = a.rank[e0 + i];
+            if (rk >= cnt) {
+                atomicOr(&a.res->err, (unsigned long long)kErrInternal);
+                continue;
             }
-        }
-        __syncthreads();
-        // hits without any ToT: plain means (the weighted sums are all zero)
-#pragma unroll
-        for (int k = 0; k < kK; ++k) {
-            const uint32_t i = tid + k * kWG;
-            if (i < n && W[root[k]] == 0) {
-                const uint32_t rr = root[k];
-                atomicAdd(&SX[rr], ev[k].x);
-                atomicAdd(&SY[rr], ev[k].y);
-                atomicAdd(&ST[rr], (unsigned long long)time_term1(a, ev[k].tot, ev[k].t));
-            }
-        }
-        __syncthreads();
-        uint32_t rank[kK];
-        uint32_t running = 0;
-#pragma unroll
-        for (int k = 0; k < kK; ++k) {
-            const uint32_t i = tid + k * kWG;
-            uint32_t tot;
-            const bool is_root = i < n && root[k] == i;
-            rank[k] = running + wg_flag_scan<kWG>(is_root, scan_tmp, &tot);
-            running += tot;
-        }
-        if (tid < 64) {
-            const uint64_t p = seg_lookback(a, ticket, running);
-            if (tid == 0) {
-                bc[1] = p;
-                if (running) atomicAdd(&a.res->n_hits, (unsigned long long)running);
-            }
-        }
-        __syncthreads();
-        const uint64_t out0 = bc[1];
-#pragma unroll
-        for (int k = 0; k < kK; ++k) {
-            const uint32_t i = tid + k * kWG;
-            if (i < n && root[k] == i)
-                write_hit(a, out0 + rank[k], ev[k].g, W[i], CNT[i], SX[i], SY[i], ST[i], TMIN[i],
-                          gidx_of(a, e0 + i));
-        }
-    }
-}
-
-// ------------------------------------------------------ global-memory segment
-template <bool kEvent>
-__device__ void seg_big(const ClusterArgs& a, uint8_t* lds, uint32_t* scan_tmp, uint64_t* bc,
-                        uint32_t g_lo, uint32_t ng, uint64_t e0, uint32_t n, uint64_t ticket) {
-    uint32_t* img = (uint32_t*)lds;  // u32[kH], all-ones = empty
-    uint32_t* par = a.g_parent + e0;
-    uint32_t* chn = a.g_chain + e0;
-    uint32_t* nxt = a.g_next + e0;
-    uint32_t* tt = a.g_t + e0;
-    uint32_t* sl = a.g_sl + e0;
-    uint32_t* xy = a.g_xy + e0;
-    const int tid = threadIdx.x;
-    const int r = (int)a.dxy;
-    const uint32_t dt = a.dt;
-    unsigned long long* err = &a.res->err;
-    if (tid == 0) atomicAdd(&a.res->big_segments, 1ull);
-    {
-        uint4* v = (uint4*)img;
-        for (int i = tid; i < kH * 4 / 16; i += kWG) v[i] = make_uint4(~0u, ~0u, ~0u, ~0u);
-    }
-    for (uint32_t i = tid; i < n; i += kWG) {
-        Ev e;
-        load_event<kEvent>(a, e0 + i, nullptr, 0, ng, false, g_lo, e, err);
-        par[i] = i;
-        chn[i] = kNone32;
-        tt[i] = e.t;
-        sl[i] = e.g;
-        xy[i] = e.x | (e.y << 8) | (e.tot << 16);
-    }
-    __syncthreads();
-    for (uint32_t i = tid; i < n; i += kWG) {
-        const uint32_t v = xy[i];
-        img[slot_of(v & 255u, (v >> 8) & 255u)] = i;
-    }
-    __syncthreads();
-    for (uint32_t i = tid; i < n; i += kWG) {
-        const uint32_t v = xy[i];
-        const uint32_t w = img[slot_of(v & 255u, (v >> 8) & 255u)];
-        if (w != i) nxt[i] = atomicExch(&chn[w], i);
-    }
-    __syncthreads();
-    for (uint32_t i = tid; i < n; i += kWG) {
-        const uint32_t v = xy[i];
-        const int x = (int)(v & 255u), y = (int)((v >> 8) & 255u);
-        for (int dy = 0; dy <= r; ++dy) {
-            const int ny = y + dy;
-            if (ny > 255) break;
-            for (int dx = (dy == 0 ? 0 : -r); dx <= r; ++dx) {
-                const int nx = x + dx;
-                if (nx < 0 || nx > 255) continue;
-                visit_slot(img, chn, nxt, tt, sl, xy, par, i, x, y, tt[i], sl[i], nx, ny,
-                           dx == 0 && dy == 0, r, dt, n, kNone32, err);
-            }
-        }
-    }
-    __syncthreads();
-    for (uint32_t i = tid; i < n; i += kWG) chn[i] = uf_find(par, i, n, err);  // root
-    __syncthreads();
-    if constexpr (kEvent) {
-        uint32_t nroot = 0;
-        for (uint32_t i = tid; i < n; i += kWG) {
-            const uint32_t rt = chn[i];
-            a.labels[orig_of(a, e0 + i)] = (uint32_t)orig_of(a, e0 + rt);
-            nroot += rt == i;
-        }
-        for (int d = 32; d > 0; d >>= 1) nroot += __shfl_xor(nroot, d, 64);
-        if (__lane_id() == 0 && nroot) atomicAdd(&a.res->n_hits, (unsigned long long)nroot);
-    } else {
-        unsigned long long* acc = (unsigned long long*)a.g_acc + 6 * e0;
-        for (uint32_t i = tid; i < n; i += kWG) {
-            acc[6 * i + 0] = 0;      // W
-            acc[6 * i + 1] = 0;      // count
-            acc[6 * i + 2] = 0;      // Sx
-            acc[6 * i + 3] = 0;      // Sy
-            acc[6 * i + 4] = 0;      // St
-            acc[6 * i + 5] = ~0ull;  // min t
-        }
-        __syncthreads();
-        for (uint32_t i = tid; i < n; i += kWG) {
-            const uint32_t rt = chn[i], v = xy[i], t = tt[i];
-            const uint32_t x = v & 255u, y = (v >> 8) & 255u, tot = v >> 16;
-            unsigned long long* q = acc + 6 * rt;
+            const uint32_t x = ev_x(pk), y = ev_y(pk), tot = ev_tot(pk), t = ev_t(pk);
+            unsigned long long* q = acc + 8 * rk;
             atomicAdd(q + 0, (unsigned long long)tot);
             atomicAdd(q + 1, 1ull);
             atomicAdd(q + 2, (unsigned long long)(tot * x));
             atomicAdd(q + 3, (unsigned long long)(tot * y));
             atomicAdd(q + 4, (unsigned long long)time_term(a, tot, t));
             atomicMin(q + 5, (unsigned long long)t);
+            atomicMin(q + 6, (unsigned long long)i);
         }
         __syncthreads();
-        for (uint32_t i = tid; i < n; i += kWG) {
-            unsigned long long* q = acc + 6 * chn[i];
-            if (q[0] == 0) {
-                const uint32_t v = xy[i];
-                atomicAdd(q + 2, (unsigned long long)(v & 255u));
-                atomicAdd(q + 3, (unsigned long long)((v >> 8) & 255u));
-                atomicAdd(q + 4, (unsigned long long)time_term1(a, v >> 16, tt[i]));
+        for (uint32_t i = tid; i < n; i += kCWG) {
+            const uint32_t rk = a.rank[e0 + i];
+            if (rk >= cnt) continue;
+            unsigned long long* q = acc + 8 * rk;
+            if (__hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+                const uint64_t pk = a.ev[e0 + i];
+                atomicAdd(q + 2, (unsigned long long)ev_x(pk));
+                atomicAdd(q + 3, (unsigned long long)ev_y(pk));
+                atomicAdd(q + 4, (unsigned long long)time_term1(a, ev_tot(pk), ev_t(pk)));
             }
         }
         __syncthreads();
-        // ranks of the roots in position order, one workgroup-wide round at a time
-        uint32_t running = 0;
-        const uint32_t rounds = (n + kWG - 1) / kWG;
-        for (uint32_t rd = 0; rd < rounds; ++rd) {
-            const uint32_t i = rd * kWG + tid;
-            uint32_t tot;
-            const bool is_root = i < n && chn[i] == i;
-            const uint32_t rk = running + wg_flag_scan<kWG>(is_root, scan_tmp, &tot);
-            if (is_root) par[i] = rk;  // parents are no longer needed: keep the rank
-            running += tot;
+        for (uint32_t c = tid; c < cnt; c += kCWG) {
+            unsigned long long* q = acc + 8 * c;
+            unsigned long long v[7];
+#pragma unroll
+            for (int w = 0; w < 7; ++w)
+                v[w] = __hip_atomic_load(q + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t p = (uint32_t)(e0 + v[6]);
+            const uint32_t g = goff_lds ? sg.g_lo + group_of(goff, 0, ng, p)
+                                        : group_of(a.grp_off, sg.g_lo, sg.g_hi, p);
+            write_hit(a, out0 + c, g, v[0], v[1], v[2], v[3], v[4], (uint32_t)v[5],
+                      gidx_of(a, e0 + v[6]));
         }
-        if (tid < 64) {
-            const uint64_t p = seg_lookback(a, ticket, running);
-            if (tid == 0) {
-                bc[1] = p;
-                if (running) atomicAdd(&a.res->n_hits, (unsigned long long)running);
-            }
-        }
-        __syncthreads();
-        const uint64_t out0 = bc[1];
-        for (uint32_t i = tid; i < n; i += kWG) {
-            if (chn[i] == i) {
-                const unsigned long long* q = acc + 6 * i;
-                write_hit(a, out0 + par[i], sl[i], q[0], q[1], q[2], q[3], q[4], (uint32_t)q[5],
-                          gidx_of(a, e0 + i));
-            }
-        }
+        return;
     }
-}
-
-// Segment table: seg_lo[k] = first group whose first event is at or after
-// k q, for k = 0..n_seg (n_seg = ceil(N / q)).  One thread per group g = 0..G
-// fills the k in (grp_off[g-1] / q, grp_off[g] / q]; g = G closes at n_seg.
-__global__ void k_seg_table(const uint32_t* __restrict__ grp_off, const unsigned long long* n_grp_dev,
-                            const unsigned long long* n_ev_dev, const unsigned long long* skip,
-                            uint32_t q, uint32_t* seg_lo) {
-    if (skip && *skip) return;
-    const uint64_t G = *n_grp_dev, N = *n_ev_dev;
-    const uint64_t n_seg = (N + q - 1) / q;
-    for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g <= G;
-         g += (uint64_t)gridDim.x * blockDim.x) {
-        // offsets never exceed N in a valid table; the clamps keep every
-        // write inside seg_lo[0..n_seg] whatever the table holds
-        const int64_t k_prev = g == 0 ? -1 : (int64_t)min<uint64_t>(grp_off[g - 1] / q, n_seg);
-        const int64_t k_hi = g == G ? (int64_t)n_seg : (int64_t)min<uint64_t>(grp_off[g] / q, n_seg);
-        for (int64_t k = k_prev + 1; k <= k_hi; ++k) seg_lo[k] = (uint32_t)g;
+    for (uint32_t c = tid; c < cnt; c += kCWG) {
+        W[c] = 0;
+        SX[c] = 0;
+        SY[c] = 0;
+        CNT[c] = 0;
+        TMIN[c] = kNone32;
+        MINP[c] = kNone32;
+        ST[c] = 0;
     }
-}
-
-void launch_seg_table(const uint32_t* grp_off, const unsigned long long* n_grp_dev,
-                      const unsigned long long* n_ev_dev, const unsigned long long* skip,
-                      uint32_t q, uint64_t max_groups, uint32_t* seg_lo, hipStream_t s) {
-    uint64_t blocks = (max_groups + 1 + 255) / 256;
-    if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(k_seg_table, dim3((unsigned)blocks), dim3(256), 0, s, grp_off, n_grp_dev,
-                       n_ev_dev, skip, q, seg_lo);
-}
-
-// One workgroup per segment.  The grid covers the largest possible number of
-// segments; workgroups whose ticket is beyond the actual count return at once.
-template <bool kEvent>
-__global__ __launch_bounds__(kWG, 2) void k_cluster(ClusterArgs a) {
-    __shared__ __attribute__((aligned(16))) uint8_t lds[kLdsMain];
-    __shared__ uint32_t scan_tmp[kWG / 64 + 1];
-    __shared__ uint64_t bc[8];
-    __shared__ uint32_t goff[kWG + 1];
-    const int tid = threadIdx.x;
-    if (tid == 0) bc[0] = atomicAdd(&a.res->seg_ticket, 1ull);
     __syncthreads();
-    const uint32_t k = __builtin_amdgcn_readfirstlane((uint32_t)bc[0]);
-    const uint64_t N = (a.skip && *a.skip) ? 0 : *a.n_ev_dev;
-    const uint64_t n_seg = (N + a.q - 1) / a.q;
-    if (k >= n_seg) return;
-    // groups whose first event lies in [k q, (k+1) q)
-    const uint32_t g_lo = a.seg_lo[k], g_hi = a.seg_lo[k + 1];
-    const uint64_t e0 = a.grp_off[g_lo], e1 = a.grp_off[g_hi];
-    if (g_hi < g_lo || e1 < e0 || e1 > N) {
-        if (tid == 0) {
+    for (uint32_t i = tid; i < n; i += kCWG) {
+        const uint64_t pk = a.ev[e0 + i];
+        const uint32_t rk = a.rank[e0 + i];
+        if (rk >= cnt) {
             atomicOr(&a.res->err, (unsigned long long)kErrInternal);
-            if (!kEvent) lb_publish(a.lb_status, k, kLbAggregate, 0);
+            continue;
         }
-        return;
+        const uint32_t x = ev_x(pk), y = ev_y(pk), tot = ev_tot(pk), t = ev_t(pk);
+        atomicAdd(&W[rk], tot);
+        atomicAdd(&SX[rk], tot * x);
+        atomicAdd(&SY[rk], tot * y);
+        atomicAdd(&CNT[rk], 1u);
+        atomicMin(&TMIN[rk], t);
+        atomicMin(&MINP[rk], i);
+        atomicAdd(&ST[rk], (unsigned long long)time_term(a, tot, t));
     }
-    const uint32_t n = (uint32_t)(e1 - e0);
-    const uint32_t ng = g_hi - g_lo;
-    if (n == 0) {
-        if constexpr (!kEvent) {
-            if (tid == 0) lb_publish(a.lb_status, k, k == 0 ? kLbInclusive : kLbAggregate, 0);
+    __syncthreads();
+    // components without any ToT: plain means (the weighted sums are all zero)
+    for (uint32_t i = tid; i < n; i += kCWG) {
+        const uint32_t rk = a.rank[e0 + i];
+        if (rk < cnt && W[rk] == 0) {
+            const uint64_t pk = a.ev[e0 + i];
+            atomicAdd(&SX[rk], ev_x(pk));
+            atomicAdd(&SY[rk], ev_y(pk));
+            atomicAdd(&ST[rk], (unsigned long long)time_term1(a, ev_tot(pk), ev_t(pk)));
         }
-        return;
     }
-    if (n <= (uint32_t)kCap) {
-        const bool goff_lds = ng <= (uint32_t)kWG;
-        if (goff_lds) {
-            for (uint32_t i = tid; i <= ng; i += kWG) goff[i] = a.grp_off[g_lo + i];
-        }
-        __syncthreads();
-        seg_small<kEvent>(a, lds, scan_tmp, bc, goff, goff_lds, g_lo, ng, e0, n, k);
-    } else {
-        seg_big<kEvent>(a, lds, scan_tmp, bc, g_lo, ng, e0, n, k);
+    __syncthreads();
+    for (uint32_t c = tid; c < cnt; c += kCWG) {
+        const uint32_t p = (uint32_t)(e0 + MINP[c]);
+        const uint32_t g = goff_lds ? sg.g_lo + group_of(goff, 0, ng, p)
+                                    : group_of(a.grp_off, sg.g_lo, sg.g_hi, p);
+        write_hit(a, out0 + c, g, W[c], CNT[c], SX[c], SY[c], ST[c], TMIN[c],
+                  gidx_of(a, e0 + MINP[c]));
     }
-    if (tid == 0) atomicMax(&a.res->max_segment, (unsigned long long)n);
 }
 
-uint64_t cluster_grid(uint64_t max_events, uint32_t q) { return max_events / q + 2; }
-
-void launch_cluster(const ClusterArgs& a, bool event_mode, uint64_t grid, hipStream_t s) {
+void launch_seg_centroid(const ClusterArgs& a, uint64_t grid, hipStream_t s) {
     if (grid == 0) return;
-    if (event_mode)
-        hipLaunchKernelGGL(k_cluster<true>, dim3((unsigned)grid), dim3(kWG), 0, s, a);
-    else
-        hipLaunchKernelGGL(k_cluster<false>, dim3((unsigned)grid), dim3(kWG), 0, s, a);
+    hipLaunchKernelGGL(k_seg_centroid, dim3((unsigned)grid), dim3(kCWG), 0, s, a);
 }
-
-int cluster_capacity() { return kCap; }
 
 }  // namespace tpx

@@ -138,6 +138,7 @@ struct DevResults {
     unsigned long long n_in;          // events handed to the cluster kernel (event mode)
     unsigned long long n_close_list;  // closed groups in a sorted group list (fallback)
     unsigned long long carry_last;    // table index of the last carried event + 1 (0 = none)
+    unsigned long long n_seg;         // cluster segments of this call
 };
 
 enum : unsigned long long {

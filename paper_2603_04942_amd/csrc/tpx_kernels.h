@@ -50,13 +50,15 @@ struct ClusterArgs {
     const float* walk;
     tpx_hit* hits;
     uint64_t hit_cap;
-    uint32_t* labels;
-    uint64_t* lb_status;       // zeroed, one word per segment
+    uint32_t* labels;          // event mode: label of every event
+    uint32_t* rank;            // stream mode: component rank of every event in its segment
+    uint32_t* seg_cnt;         // stream mode: components per segment
+    const uint32_t* seg_off;   // stream mode: exclusive prefix of seg_cnt, [n_seg + 1]
     DevResults* res;
     const unsigned long long* skip;  // non-zero: do nothing (events not in shot order)
     // per-event scratch for segments that do not fit in LDS
     uint32_t *g_parent, *g_chain, *g_next, *g_t, *g_sl, *g_xy;
-    uint64_t* g_acc;           // 6 words per event
+    uint64_t* g_acc;           // 8 words per event
 };
 
 void launch_tile_summary(const uint64_t* pk, uint64_t n, uint32_t sub, uint64_t jump,
@@ -75,7 +77,10 @@ void launch_cluster(const ClusterArgs& a, bool event_mode, uint64_t grid, hipStr
 // max_events / q + 2 entries
 void launch_seg_table(const uint32_t* grp_off, const unsigned long long* n_grp_dev,
                       const unsigned long long* n_ev_dev, const unsigned long long* skip,
-                      uint32_t q, uint64_t max_groups, uint32_t* seg_lo, hipStream_t s);
+                      uint32_t q, uint64_t max_groups, uint32_t* seg_lo, DevResults* res,
+                      hipStream_t s);
+// stream mode: moments and hits of the components found by launch_cluster
+void launch_seg_centroid(const ClusterArgs& a, uint64_t grid, hipStream_t s);
 // workgroups needed to cover every segment of up to max_events events
 uint64_t cluster_grid(uint64_t max_events, uint32_t q);
 int cluster_capacity();

@@ -133,6 +133,36 @@ def test_stream_chunked(tpx, orc, seed):
     assert s.fallback_count == 0
 
 
+@pytest.mark.parametrize("n_iso", [1500, 3000, 20000])
+def test_stream_many_components(tpx, orc, n_iso):
+    """One shot whose pixels are all isolated (spacing 2 on the grid, so no
+    two are neighbours) plus one 3x3 blob: more components in one segment
+    than the LDS accumulators hold (n_iso = 1500), a segment beyond the LDS
+    event capacity (3000), and one shot of 20000 events spanning many
+    segment strides."""
+    _say(f"many components n_iso={n_iso}")
+    rng = np.random.default_rng(n_iso)
+    trig = np.array([1_000_000, 1_000_000 + synth.SHOT_PERIOD_TICKS])
+    k = np.arange(n_iso)
+    x = 2 * (k % 128)
+    y = 2 * ((k // 128) % 128)
+    t = trig[0] + 100 + (k // 16384) * 1000 + rng.integers(0, 50_000, n_iso)
+    bx, by = np.meshgrid(np.arange(3) + 1, np.arange(3) + 1)
+    x = np.concatenate([x, bx.ravel()])
+    y = np.concatenate([y, by.ravel()])
+    t = np.concatenate([t, np.full(9, trig[0] + 60_000)])
+    tot = rng.integers(0, 400, x.size)
+    tot[:5] = 0
+    order = np.argsort(t, kind="stable")
+    pk = np.concatenate([synth.encode_tdc(trig[:1], [0]),
+                         synth.encode_pixels(x[order], y[order], tot[order], t[order]),
+                         synth.encode_tdc(trig[1:], [1])])
+    ref, _ = orc.run(pk)
+    assert ref.size > 1024
+    h, _ = tpx.process_stream(pk)
+    assert_hits_match(h, ref)
+
+
 def test_stream_out_of_order_takes_general_path(tpx, orc):
     """A kept pixel of one shot reported after pixels of the next shot: the
     events are not in shot order and the general sorting path must give the
