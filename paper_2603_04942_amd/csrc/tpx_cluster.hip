@@ -42,7 +42,8 @@ constexpr int kOffPar = 32768;         // u32[kCap] union-find parent
 constexpr int kOffEv = 40960;          // u64[kCap] x | y << 8 | group start << 16 | t << 32
 constexpr int kOffChn = 57344;         // u32[kCap] first chained event of a slot owner
 constexpr int kOffNxt = 65536;         // u16[kCap] next chained event
-constexpr int kLdsMain = 69632;
+constexpr int kOffMsk = 69632;         // u32[kCap] neighbour mask (3x3 box)
+constexpr int kLdsMain = 77824;
 static_assert(4 * kH <= kLdsMain, "big-path image");
 
 __device__ inline uint32_t slot_of(uint32_t x, uint32_t y) { return ((y & 63u) << 8) | x; }
@@ -232,12 +233,127 @@ __device__ inline bool box_events(const uint16_t* img, const uint32_t* chn, cons
     return ok;
 }
 
+// Edge test for a candidate taken from image slot (x + dx, (y + dy) & 63): x
+// matches by construction, y up to multiples of 64.
+__device__ inline bool is_edge_slot(uint64_t me, uint64_t o, int dy, uint32_t dt) {
+    const uint32_t ya = (uint32_t)(me >> 8) & 255u, yb = (uint32_t)(o >> 8) & 255u;
+    return ((me ^ o) & 0xFFFF0000ull) == 0 &&                           // same group
+           absdiff((uint32_t)(me >> 32), (uint32_t)(o >> 32)) <= dt &&  // |dt|
+           yb == ya + (uint32_t)dy;
+}
+
 __device__ inline bool is_edge(uint64_t me, uint64_t o, int r, uint32_t dt) {
     const uint32_t ya = (uint32_t)(me >> 8) & 255u, yb = (uint32_t)(o >> 8) & 255u;
     const uint32_t xa = (uint32_t)me & 255u, xb = (uint32_t)o & 255u;
     return ((me ^ o) & 0xFFFF0000ull) == 0 &&                           // same group
            absdiff((uint32_t)(me >> 32), (uint32_t)(o >> 32)) <= dt &&  // |dt|
            absdiff(ya, yb) <= (uint32_t)r && absdiff(xa, xb) <= (uint32_t)r;
+}
+
+// ---------------------------------------------------- 3x3 box (r = 1)
+// Slot s of the box is (x + s % 3 - 1, y + s / 3 - 1).  Every event sees the
+// owner of each slot and the first event chained behind it (18 candidates).
+// Mask bit s: the owner of slot s is a neighbour; bit 9 + s: its first chained
+// event is.  An event deeper in a chain (kDeep) is invisible to the others, so
+// it records its edges to the 18 candidates whatever their positions and
+// walks the rest of the chains itself; otherwise only candidates with smaller
+// positions are recorded, so that every edge is recorded once.
+constexpr uint32_t kDeep = 1u << 18;
+constexpr uint32_t kMaxRounds = 64;
+
+__device__ inline bool box3_slot(int x, int y, int s, uint32_t* slot) {
+    const int nx = x + s % 3 - 1, ny = y + s / 3 - 1;
+    *slot = slot_of((uint32_t)nx, (uint32_t)ny);
+    return nx >= 0 && nx <= 255 && ny >= 0 && ny <= 255;
+}
+
+// Candidate 0..17 of event v: owners, then first chained events (kNone32 if
+// none).
+__device__ inline void box3_cands(const uint16_t* img, const uint32_t* chn, uint64_t v,
+                                  uint32_t* c) {
+    const int x = (int)(v & 255u), y = (int)((v >> 8) & 255u);
+#pragma unroll
+    for (int s = 0; s < 9; ++s) {
+        uint32_t slot;
+        const bool in = box3_slot(x, y, s, &slot);
+        const uint32_t w = in ? (uint32_t)img[slot] : kNone16;
+        c[s] = w == kNone16 ? kNone32 : w;
+    }
+#pragma unroll
+    for (int s = 0; s < 9; ++s) c[9 + s] = c[s] == kNone32 ? kNone32 : chn[c[s]];
+}
+
+// Mask of event i (see above) and its smallest recorded neighbour (or i).
+__device__ inline uint32_t box3_visit(const uint16_t* img, const uint32_t* chn,
+                                      const uint16_t* nxt, const uint64_t* evs, uint32_t i,
+                                      uint32_t dt, uint32_t* m_out) {
+    const uint64_t v = evs[i];
+    uint32_t c[18];
+    box3_cands(img, chn, v, c);
+    uint64_t e[18];
+#pragma unroll
+    for (int s = 0; s < 18; ++s) e[s] = evs[c[s] == kNone32 ? i : c[s]];
+    // i is deep when it is neither the owner nor the first chained event of
+    // its own slot
+    const bool deep = c[4] != i && c[13] != i;
+    uint32_t m = i, mask = deep ? kDeep : 0u;
+#pragma unroll
+    for (int s = 0; s < 18; ++s) {
+        const uint32_t j = c[s];
+        const bool ed = j != kNone32 && j != i && (deep || j < i) &&
+                        is_edge_slot(v, e[s], (s % 9) / 3 - 1, dt);
+        mask |= ed ? (1u << s) : 0u;
+        m = (ed && j < m) ? j : m;
+    }
+    *m_out = m;
+    return mask;
+}
+
+// Calls f(q) for every event q != i chained at depth two or more in the box
+// of v with an edge to v.  False when a chain is longer than the segment.
+template <typename F>
+__device__ inline bool box3_deep_edges(const uint16_t* img, const uint32_t* chn,
+                                       const uint16_t* nxt, const uint64_t* evs, uint32_t i,
+                                       uint64_t v, uint32_t dt, uint32_t n, F&& f) {
+    uint32_t c[18];
+    box3_cands(img, chn, v, c);
+    bool ok = true;
+    for (int s = 9; s < 18; ++s) {
+        if (c[s] == kNone32) continue;
+        const uint32_t first = nxt[c[s]];
+        uint32_t q = first == kNone16 ? kNone32 : first, steps = 0;
+        while (q != kNone32) {
+            if (q != i && is_edge(v, evs[q], 1, dt)) f(q);
+            if (++steps > n) {
+                ok = false;
+                break;
+            }
+            const uint32_t nn = nxt[q];
+            q = nn == kNone16 ? kNone32 : nn;
+        }
+    }
+    return ok;
+}
+
+// Hooks the larger of two distinct tree roots under the smaller if it is
+// still a root: trees only ever merge, so two events once seen in one tree
+// stay in one tree.  False when the root was taken by another hook first (the
+// edge is then seen again in the next round).
+__device__ inline bool hook(uint32_t* par, uint32_t ra, uint32_t rb) {
+    const uint32_t hi = ra > rb ? ra : rb, lo = ra > rb ? rb : ra;
+    uint32_t expect = hi;
+    return __hip_atomic_compare_exchange_strong(par + hi, &expect, lo, __ATOMIC_RELAXED,
+                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Points every event at its root (pointer jumping; concurrent readers see an
+// old parent or a root, both ancestors).
+__device__ inline void compress_all(uint32_t* par, uint32_t n, int tid, int nthreads) {
+    for (uint32_t i = tid; i < n; i += nthreads) {
+        uint32_t p = ald(par + i), steps = 0;
+        for (uint32_t nx; p != (nx = ald(par + p)) && ++steps <= n;) p = nx;
+        ast(par + i, p);
+    }
 }
 
 // ------------------------------------------------------------ LDS segment
@@ -251,6 +367,7 @@ __device__ void seg_small(const ClusterArgs& a, uint8_t* lds, uint32_t* scan_tmp
     uint64_t* evs = (uint64_t*)(lds + kOffEv);
     uint32_t* chn = (uint32_t*)(lds + kOffChn);
     uint16_t* nxt = (uint16_t*)(lds + kOffNxt);
+    uint32_t* msk = (uint32_t*)(lds + kOffMsk);
     const int tid = threadIdx.x;
     const int r = (int)a.dxy;
     const uint32_t dt = a.dt, n = sg.n;
@@ -284,39 +401,89 @@ __device__ void seg_small(const ClusterArgs& a, uint8_t* lds, uint32_t* scan_tmp
         }
     }
     __syncthreads();
-    // every event points at the smallest of itself and its neighbours
     bool ok = true;
-    for (uint32_t i = tid; i < n; i += kWG) {
-        uint32_t m = i;
-        const uint64_t v = evs[i];
-        ok &= box_events<R>(img, chn, nxt, i, (int)(v & 255u), (int)((v >> 8) & 255u), r, n,
-                            [&](uint32_t j, bool) {
-                                if (j < m && is_edge(v, evs[j], r, dt)) m = j;
-                            });
-        par[i] = m;
-    }
-    __syncthreads();
-    // path compression: every event points at the root of its tree (a
-    // concurrent reader sees the old parent or the root, both ancestors)
-    for (uint32_t i = tid; i < n; i += kWG) {
-        uint32_t p = ald(par + i), steps = 0;
-        for (uint32_t nx; p != (nx = ald(par + p)) && ++steps <= n;) p = nx;
-        ast(par + i, p);
-    }
-    __syncthreads();
-    // edges between different trees
-    for (uint32_t i = tid; i < n; i += kWG) {
-        const uint64_t v = evs[i];
-        ok &= box_events<R>(img, chn, nxt, i, (int)(v & 255u), (int)((v >> 8) & 255u), r, n,
-                            [&](uint32_t j, bool fwd) {
-                                if (fwd && ald(par + j) != ald(par + i) && is_edge(v, evs[j], r, dt))
-                                    uf_unite(par, i, j, n, err);
-                            });
+    if constexpr (R == 1) {
+        // every event points at its smallest recorded neighbour (or itself):
+        // a forest whose roots are local minima
+        for (uint32_t i = tid; i < n; i += kWG) {
+            uint32_t m;
+            const uint32_t mask = box3_visit(img, chn, nxt, evs, i, dt, &m);
+            if (mask & kDeep)
+                ok &= box3_deep_edges(img, chn, nxt, evs, i, evs[i], dt, n,
+                                      [&](uint32_t q) { m = q < m ? q : m; });
+            par[i] = m;
+            msk[i] = mask;
+        }
+        __syncthreads();
+        compress_all(par, n, tid, kWG);
+        __syncthreads();
+        // rounds of root hooks over the recorded edges, then pointer jumping;
+        // an edge whose ends share a tree, or whose hook took, is dropped for
+        // good (trees never split); a round in which every hook took ends it
+        for (uint32_t round = 0;; ++round) {
+            bool changed = false;  // some edge still to be seen again
+            for (uint32_t i = tid; i < n; i += kWG) {
+                uint32_t mask = msk[i];
+                if (!mask) continue;
+                const uint64_t v = evs[i];
+                uint32_t c[18];
+                box3_cands(img, chn, v, c);
+                const uint32_t ri = ald(par + i);
+                uint32_t keep = mask & kDeep;
+#pragma unroll
+                for (int s = 0; s < 18; ++s) {
+                    if ((mask >> s) & 1u) {
+                        const uint32_t rj = ald(par + c[s]);
+                        if (rj != ri && !hook(par, ri, rj)) {
+                            keep |= 1u << s;
+                            changed = true;
+                        }
+                    }
+                }
+                if (mask & kDeep)
+                    ok &= box3_deep_edges(img, chn, nxt, evs, i, v, dt, n, [&](uint32_t q) {
+                        const uint32_t ra = ald(par + i), rq = ald(par + q);
+                        if (q < i && ra != rq && !hook(par, ra, rq)) changed = true;
+                    });
+                if (keep != mask) msk[i] = keep;
+            }
+            __syncthreads();
+            compress_all(par, n, tid, kWG);
+            if (!__syncthreads_or(changed)) break;
+            if (round >= kMaxRounds) {  // far more rounds than any forest needs
+                if (tid == 0) atomicOr(err, (unsigned long long)kErrLoopUnite);
+                break;
+            }
+        }
+    } else {
+        // every event points at the smallest of itself and its neighbours
+        for (uint32_t i = tid; i < n; i += kWG) {
+            uint32_t m = i;
+            const uint64_t v = evs[i];
+            ok &= box_events<R>(img, chn, nxt, i, (int)(v & 255u), (int)((v >> 8) & 255u), r, n,
+                                [&](uint32_t j, bool) {
+                                    if (j < m && is_edge(v, evs[j], r, dt)) m = j;
+                                });
+            par[i] = m;
+        }
+        __syncthreads();
+        compress_all(par, n, tid, kWG);
+        __syncthreads();
+        // edges between different trees
+        for (uint32_t i = tid; i < n; i += kWG) {
+            const uint64_t v = evs[i];
+            ok &= box_events<R>(img, chn, nxt, i, (int)(v & 255u), (int)((v >> 8) & 255u), r, n,
+                                [&](uint32_t j, bool fwd) {
+                                    if (fwd && ald(par + j) != ald(par + i) &&
+                                        is_edge(v, evs[j], r, dt))
+                                        uf_unite(par, i, j, n, err);
+                                });
+        }
+        __syncthreads();
+        // final roots, stored as parents
+        for (uint32_t i = tid; i < n; i += kWG) ast(par + i, uf_find(par, i, n, err));
     }
     if (!ok) atomicOr(err, (unsigned long long)kErrLoopChain);
-    __syncthreads();
-    // final roots, stored as parents
-    for (uint32_t i = tid; i < n; i += kWG) ast(par + i, uf_find(par, i, n, err));
     __syncthreads();
 
     if constexpr (kEvent) {

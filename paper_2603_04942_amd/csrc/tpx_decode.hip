@@ -398,10 +398,19 @@ __global__ __launch_bounds__(kTileThreads) void k_assign(AssignArgs a) {
         }
         fmin = min(fmin, (uint32_t)__shfl_xor(fmin, d, 64));
     }
-    uint32_t stat[8] = {npix, nother, npre, ncut, nlate, fwd, back, 0};
+    // the seven per-thread counts (each <= 16) in 16-bit fields of two words
+    uint64_t st0 = (uint64_t)npix | ((uint64_t)nother << 16) | ((uint64_t)npre << 32) |
+                   ((uint64_t)ncut << 48);
+    uint64_t st1 = (uint64_t)nlate | ((uint64_t)fwd << 16) | ((uint64_t)back << 32);
 #pragma unroll
-    for (int k = 0; k < 7; ++k)
-        for (int d = 32; d > 0; d >>= 1) stat[k] += __shfl_xor(stat[k], d, 64);
+    for (int d = 32; d > 0; d >>= 1) {
+        st0 += __shfl_xor(st0, d, 64);
+        st1 += __shfl_xor(st1, d, 64);
+    }
+    const uint32_t stat[7] = {(uint32_t)(st0 & 0xFFFF), (uint32_t)((st0 >> 16) & 0xFFFF),
+                              (uint32_t)((st0 >> 32) & 0xFFFF), (uint32_t)(st0 >> 48),
+                              (uint32_t)(st1 & 0xFFFF), (uint32_t)((st1 >> 16) & 0xFFFF),
+                              (uint32_t)((st1 >> 32) & 0xFFFF)};
     uint64_t tm = tmax1;
     for (int d = 32; d > 0; d >>= 1) tm = max(tm, (uint64_t)__shfl_xor(tm, d, 64));
     if (__lane_id() == 63) {

@@ -96,7 +96,7 @@ __host__ __device__ inline uint32_t ev_x(uint64_t p) { return (uint32_t)(p >> 48
 constexpr int kTileThreads = 256;
 constexpr int kTileItems = 16;
 constexpr int kTilePkts = kTileThreads * kTileItems;  // 4096 words = 32 KB
-constexpr int kTrigSlice = 1024;                       // triggers staged in LDS
+constexpr int kTrigSlice = 512;                        // triggers staged in LDS
 
 // Fold of a run of tiles: pixel and trigger counter runs, trigger words.
 struct TileAcc {
