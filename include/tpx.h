@@ -190,8 +190,8 @@ uint64_t tpx_stream_fallback_count(const tpx_stream* s);
 /* Diagnostics: per-stage device time of the last tpx_process_stream call on
  * the fast path, in ms, measured with HIP events recorded on the call's
  * stream between the stages (tile_summary, tile_prefix, assign, group,
- * cluster, carry).  Enabling creates the events; timing adds one event
- * record per stage and nothing else. */
+ * cluster, centroid, carry).  Enabling creates the events; timing adds one
+ * event record per stage and nothing else. */
 tpx_status tpx_stream_set_timing(tpx_stream* s, int enable);
 tpx_status tpx_stream_get_timing(const tpx_stream* s, float* ms_h, size_t n,
                                  size_t* n_stages_h);

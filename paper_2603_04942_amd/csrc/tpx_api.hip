@@ -32,6 +32,7 @@ tpx_status fail(tpx_status st, const char* fmt, ...) {
     } while (0)
 
 constexpr uint32_t kQ = 1024;           // segment stride (events)
+constexpr int kStages = 7;              // timed stages of the stream fast path
 constexpr uint64_t kMaxEvents = 0xFFFFFFF0ull;
 // packets in one decode call: the tile look-back keeps a kept-event count and a
 // trigger-table index in 31 bits each
@@ -451,8 +452,8 @@ struct tpx_stream {
     uint64_t n_fallback;    // chunks that needed the general (sorting) path
     // optional per-stage timing with HIP events on the caller's stream
     int timing;
-    hipEvent_t tev[8];
-    float stage_ms[7];
+    hipEvent_t tev[kStages + 1];
+    float stage_ms[kStages];
 };
 
 namespace {
@@ -553,8 +554,8 @@ void stream_front(tpx_stream* s, const uint64_t* chunk, uint64_t n, hipStream_t 
 tpx_status stream_fast(tpx_stream* s, const uint64_t* chunk, uint64_t n, int flush, tpx_hit* hits,
                        uint64_t hit_cap, hipStream_t hs) {
     stream_front(s, chunk, n, hs);
-    const uint64_t rows = s->n_win + n + 1;
-    launch_fill_u32(s->shot_cnt, 0, rows + 1, hs);
+    const uint64_t rows = s->n_win + n + 1;  // bound of the table rows (window + new triggers)
+    launch_fill_u32_dev(s->shot_cnt, 0, s->n_win, &s->res->n_trig, 2, hs);
     launch_carry_in(s->c_ev[s->cur], s->c_shot[s->cur], s->n_carry, s->carry_rebase, s->ev, nullptr,
                     s->shot_cnt, hs);
     AssignArgs a = stream_assign_args(s, chunk, n);
@@ -577,17 +578,19 @@ tpx_status stream_fast(tpx_stream* s, const uint64_t* chunk, uint64_t n, int flu
     mark(s, 4, hs);
     const uint64_t grid = cluster_grid(s->n_carry + n, kQ);
     launch_cluster(c, false, grid, hs);
+    mark(s, 5, hs);
     launch_scan_u32(s->seg_cnt, s->seg_off, 0, &s->res->n_seg, s->block_tmp, hs);
     launch_seg_centroid(c, grid, hs);
-    mark(s, 5, hs);
+    mark(s, 6, hs);
     const int nx = 1 - s->cur;
     launch_carry_out(s->ev, nullptr, nullptr, s->shot_off, &s->res->n_groups, &s->res->n_close_ev,
                      &s->res->n_kept, s->c_gidx[s->cur], s->n_carry, s->ev_next, s->c_ev[nx],
                      s->c_shot[nx], s->c_gidx[nx], s->carry_cap, s->res, hs);
-    mark(s, 6, hs);
+    mark(s, 7, hs);
     tpx_status rc = read_res(s->res, s->res_h, hs);
     if (rc == TPX_OK && s->timing)
-        for (int i = 0; i < 6; ++i) (void)hipEventElapsedTime(&s->stage_ms[i], s->tev[i], s->tev[i + 1]);
+        for (int i = 0; i < kStages; ++i)
+            (void)hipEventElapsedTime(&s->stage_ms[i], s->tev[i], s->tev[i + 1]);
     return rc;
 }
 
@@ -869,8 +872,8 @@ tpx_status tpx_stream_set_state(tpx_stream* s, const void* buf_h, size_t bytes) 
 // Diagnostics for tests and benchmarks: chunks that took the general path.
 uint64_t tpx_stream_fallback_count(const tpx_stream* s) { return s ? s->n_fallback : 0; }
 
-static const char* const kStageNames[6] = {"tile_summary", "tile_prefix", "assign",
-                                           "group",        "cluster",     "carry"};
+static const char* const kStageNames[kStages] = {"tile_summary", "tile_prefix", "assign", "group",
+                                                 "cluster",      "centroid",    "carry"};
 
 tpx_status tpx_stream_set_timing(tpx_stream* s, int enable) {
     if (!s) return fail(TPX_EINVAL, "stream is NULL");
@@ -886,12 +889,12 @@ tpx_status tpx_stream_set_timing(tpx_stream* s, int enable) {
 
 tpx_status tpx_stream_get_timing(const tpx_stream* s, float* ms_h, size_t n, size_t* n_stages_h) {
     if (!s || !n_stages_h) return fail(TPX_EINVAL, "NULL argument");
-    *n_stages_h = 6;
+    *n_stages_h = kStages;
     if (!s->timing) return fail(TPX_EINVAL, "timing is not enabled");
-    for (size_t i = 0; i < n && i < 6; ++i) ms_h[i] = s->stage_ms[i];
+    for (size_t i = 0; i < n && i < (size_t)kStages; ++i) ms_h[i] = s->stage_ms[i];
     return TPX_OK;
 }
 
-const char* tpx_stream_stage_name(size_t i) { return i < 6 ? kStageNames[i] : ""; }
+const char* tpx_stream_stage_name(size_t i) { return i < (size_t)kStages ? kStageNames[i] : ""; }
 
 }  // extern "C"

@@ -423,21 +423,23 @@ __device__ void seg_small(const ClusterArgs& a, uint8_t* lds, uint32_t* scan_tmp
         for (uint32_t round = 0;; ++round) {
             bool changed = false;  // some edge still to be seen again
             for (uint32_t i = tid; i < n; i += kWG) {
-                uint32_t mask = msk[i];
+                const uint32_t mask = msk[i];
                 if (!mask) continue;
                 const uint64_t v = evs[i];
-                uint32_t c[18];
-                box3_cands(img, chn, v, c);
+                const int x = (int)(v & 255u), y = (int)((v >> 8) & 255u);
                 const uint32_t ri = ald(par + i);
                 uint32_t keep = mask & kDeep;
-#pragma unroll
-                for (int s = 0; s < 18; ++s) {
-                    if ((mask >> s) & 1u) {
-                        const uint32_t rj = ald(par + c[s]);
-                        if (rj != ri && !hook(par, ri, rj)) {
-                            keep |= 1u << s;
-                            changed = true;
-                        }
+                // the recorded candidates only, one set bit at a time
+                for (uint32_t bits = mask & (kDeep - 1); bits; bits &= bits - 1) {
+                    const int s = __builtin_ctz(bits);
+                    uint32_t slot;
+                    box3_slot(x, y, s % 9, &slot);
+                    const uint32_t w = img[slot];
+                    const uint32_t j = s < 9 ? w : chn[w];
+                    const uint32_t rj = ald(par + j);
+                    if (rj != ri && !hook(par, ri, rj)) {
+                        keep |= 1u << s;
+                        changed = true;
                     }
                 }
                 if (mask & kDeep)

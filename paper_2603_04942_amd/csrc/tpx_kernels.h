@@ -87,6 +87,8 @@ int cluster_capacity();
 
 // utilities (tpx_util.hip)
 void launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
+void launch_fill_u32_dev(uint32_t* p, uint32_t v, uint64_t base, const unsigned long long* n_dev,
+                         uint64_t extra, hipStream_t s);
 void launch_fill_u64(uint64_t* p, uint64_t v, uint64_t n, hipStream_t s);
 // out[0..n] = exclusive prefix of in[0..n), out[n] = total; n = *n_dev if n_dev
 void launch_scan_u32(const uint32_t* in, uint32_t* out, uint64_t n_host,

@@ -24,6 +24,19 @@ __global__ void k_fill_u64(uint64_t* p, uint64_t v, uint64_t n) {
          i += (uint64_t)gridDim.x * blockDim.x)
         p[i] = v;
 }
+// p[0 .. base + *n_dev + extra) = v, the count read on the device
+__global__ void k_fill_u32_dev(uint32_t* p, uint32_t v, uint64_t base,
+                               const unsigned long long* n_dev, uint64_t extra) {
+    const uint64_t n = base + *n_dev + extra;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+void launch_fill_u32_dev(uint32_t* p, uint32_t v, uint64_t base, const unsigned long long* n_dev,
+                         uint64_t extra, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_u32_dev, dim3(256), dim3(256), 0, s, p, v, base, n_dev, extra);
+}
+
 void launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s) {
     if (n) hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, p, v, n);
 }
