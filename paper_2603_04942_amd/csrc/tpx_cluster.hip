@@ -853,17 +853,22 @@ __global__ __launch_bounds__(kCWG) void k_seg_centroid(ClusterArgs a) {
         atomicAdd(&ST[rk], (unsigned long long)time_term(a, tot, t));
     }
     __syncthreads();
-    // components without any ToT: plain means (the weighted sums are all zero)
-    for (uint32_t i = tid; i < n; i += kCWG) {
-        const uint32_t rk = a.rank[e0 + i];
-        if (rk < cnt && W[rk] == 0) {
-            const uint64_t pk = a.ev[e0 + i];
-            atomicAdd(&SX[rk], ev_x(pk));
-            atomicAdd(&SY[rk], ev_y(pk));
-            atomicAdd(&ST[rk], (unsigned long long)time_term1(a, ev_tot(pk), ev_t(pk)));
+    // components without any ToT: plain means (the weighted sums are all
+    // zero); the second pass runs only when such a component exists
+    bool zero = false;
+    for (uint32_t c = tid; c < cnt; c += kCWG) zero |= W[c] == 0;
+    if (__syncthreads_or(zero)) {
+        for (uint32_t i = tid; i < n; i += kCWG) {
+            const uint32_t rk = a.rank[e0 + i];
+            if (rk < cnt && W[rk] == 0) {
+                const uint64_t pk = a.ev[e0 + i];
+                atomicAdd(&SX[rk], ev_x(pk));
+                atomicAdd(&SY[rk], ev_y(pk));
+                atomicAdd(&ST[rk], (unsigned long long)time_term1(a, ev_tot(pk), ev_t(pk)));
+            }
         }
+        __syncthreads();
     }
-    __syncthreads();
     for (uint32_t c = tid; c < cnt; c += kCWG) {
         const uint32_t p = (uint32_t)(e0 + MINP[c]);
         const uint32_t g = goff_lds ? sg.g_lo + group_of(goff, 0, ng, p)

@@ -74,8 +74,9 @@ __device__ inline TileAcc wave_acc_inscan(TileAcc v, uint64_t jump) {
     return v;
 }
 
-// Exclusive in-order fold of one RunSum per thread over the workgroup; *all
-// gets the fold of every thread.  wbuf holds one entry per wave.
+// Exclusive in-order fold of one RunSum per thread over a workgroup of NW
+// waves; *all gets the fold of every thread.  wbuf holds one entry per wave.
+template <int NW = kWaves>
 __device__ inline RunSum wg_run_exscan(RunSum v, RunSum* wbuf, uint64_t jump, RunSum* all) {
     const RunSum inc = wave_run_inscan(v, jump);
     RunSum ex = shfl_up_run(inc, 1);
@@ -85,7 +86,7 @@ __device__ inline RunSum wg_run_exscan(RunSum v, RunSum* wbuf, uint64_t jump, Ru
     __syncthreads();
     RunSum pre = run_empty(), tot = run_empty();
 #pragma unroll
-    for (int k = 0; k < kWaves; ++k) {
+    for (int k = 0; k < NW; ++k) {
         const RunSum c = wbuf[k];
         if (k < w) pre = run_combine(pre, c, jump);
         tot = run_combine(tot, c, jump);
@@ -116,44 +117,56 @@ __device__ inline TileAcc wg1024_acc_exscan(TileAcc v, TileAcc* wbuf, uint64_t j
 }
 
 // ------------------------------------------------------------------ summary
-__global__ __launch_bounds__(kTileThreads) void k_tile_summary(const uint64_t* __restrict__ pk,
-                                                              uint64_t n, uint32_t sub,
-                                                              uint64_t jump, TileAcc* sums,
-                                                              uint64_t* tdc_slot) {
-    __shared__ uint64_t sp[kTileLds];
-    __shared__ RunSum wbuf[kWaves];
-    __shared__ uint32_t tmp[kWaves + 1];
+// 512 threads of 8 consecutive words per tile (more waves per CU than the
+// assignment pass, which keeps 16 words per thread in registers).
+constexpr int kSumThreads = 512;
+constexpr int kSumItems = kTilePkts / kSumThreads;
+constexpr int kSumWaves = kSumThreads / 64;
+__device__ inline int sum_slot(int i) { return i + (i >> 3); }
+
+__global__ __launch_bounds__(kSumThreads) void k_tile_summary(const uint64_t* __restrict__ pk,
+                                                             uint64_t n, uint32_t sub,
+                                                             uint64_t jump, TileAcc* sums,
+                                                             uint64_t* tdc_slot) {
+    __shared__ uint64_t sp[kTilePkts + kTilePkts / 8];
+    __shared__ RunSum wbuf[kSumWaves];
+    __shared__ uint32_t tmp[kSumWaves + 1];
     const uint64_t tile = blockIdx.x;
     const uint64_t base = tile * kTilePkts;
-    load_tile(pk, base, n, sp);
+#pragma unroll
+    for (int k = 0; k < kSumItems; ++k) {
+        const int i = k * kSumThreads + threadIdx.x;
+        const uint64_t g = base + (uint64_t)i;
+        sp[sum_slot(i)] = g < n ? __builtin_nontemporal_load(pk + g) : 0ull;
+    }
     __syncthreads();
     const int nvalid = (int)min<uint64_t>((uint64_t)kTilePkts, n - base);
     RunSum P = run_empty(), T = run_empty();
 #pragma unroll
-    for (int j = 0; j < kTileItems; ++j) {
-        const int i = threadIdx.x * kTileItems + j;
+    for (int j = 0; j < kSumItems; ++j) {
+        const int i = threadIdx.x * kSumItems + j;
         if (i < nvalid) {
-            const Word d = decode_word(sp[tile_slot(i)], sub);
+            const Word d = decode_word(sp[sum_slot(i)], sub);
             if (d.kind == kPixel) P = run_push(P, d.raw, jump);
             else if (d.kind == kTrigger) T = run_push(T, d.raw, jump);
         }
     }
     uint32_t ntot;
     const uint32_t nt = (uint32_t)T.count;
-    const uint32_t pos = wg_count_scan<kTileThreads>(nt, tmp, &ntot);
+    const uint32_t pos = wg_count_scan<kSumThreads>(nt, tmp, &ntot);
     if (nt) {
         uint32_t q = 0;
-        for (int j = 0; j < kTileItems; ++j) {
-            const int i = threadIdx.x * kTileItems + j;
+        for (int j = 0; j < kSumItems; ++j) {
+            const int i = threadIdx.x * kSumItems + j;
             if (i < nvalid) {
-                const Word d = decode_word(sp[tile_slot(i)], sub);
+                const Word d = decode_word(sp[sum_slot(i)], sub);
                 if (d.kind == kTrigger) tdc_slot[base + pos + q++] = d.raw;
             }
         }
     }
     RunSum ap, at;
-    wg_run_exscan(P, wbuf, jump, &ap);
-    wg_run_exscan(T, wbuf, jump, &at);
+    wg_run_exscan<kSumWaves>(P, wbuf, jump, &ap);
+    wg_run_exscan<kSumWaves>(T, wbuf, jump, &at);
     if (threadIdx.x == 0) sums[tile] = TileAcc{ap, at, ntot};
 }
 
@@ -284,56 +297,37 @@ __global__ __launch_bounds__(kTileThreads) void k_assign(AssignArgs a) {
     __syncthreads();
     const int nvalid = (int)min<uint64_t>((uint64_t)kTilePkts, a.n - base);
 
-    // this thread's run of pixel counter values, folded across the workgroup
+    // every word decoded once: a pixel as raw tick | x << 34 | y << 42 |
+    // ToT << 50, anything else as a marker; the thread's run of pixel counter
+    // values is folded across the workgroup
+    constexpr uint64_t kNotPixel = 1ull << 63, kOtherWord = 1ull << 62;
+    uint64_t tv[kTileItems];
     RunSum P = run_empty();
 #pragma unroll
     for (int j = 0; j < kTileItems; ++j) {
         const int i = threadIdx.x * kTileItems + j;
+        tv[j] = kNotPixel;
         if (i < nvalid) {
             const Word d = decode_word(sp[tile_slot(i)], a.sub);
-            if (d.kind == kPixel) P = run_push(P, d.raw, a.jump);
+            if (d.kind == kPixel) {
+                tv[j] = d.raw | ((uint64_t)d.x << 34) | ((uint64_t)d.y << 42) | ((uint64_t)d.tot << 50);
+                P = run_push(P, d.raw, a.jump);
+            } else if (d.kind == kOther) {
+                tv[j] = kNotPixel | kOtherWord;
+            }
         }
     }
     RunSum all;
     const RunSum pre = run_combine(e.pix, wg_run_exscan(P, wbuf, a.jump, &all), a.jump);
 
-    // unwrap this thread's pixels
-    uint64_t tv[kTileItems];
+    // unwrap, then the shot of each pixel (latest trigger at or before it),
+    // ToF cut, keep; tv[j] becomes the kept event (or ~0)
     bool has = pre.count > 0;
     uint64_t last = pre.last;
     int64_t epoch = e.pix_epoch + (pre.sum - e.pix.sum);
     uint64_t tmax1 = 0;
     uint32_t fwd = 0, back = 0, npix = 0, nother = 0;
     unsigned long long err = 0;
-#pragma unroll
-    for (int j = 0; j < kTileItems; ++j) {
-        const int i = threadIdx.x * kTileItems + j;
-        tv[j] = ~0ull;
-        if (i < nvalid) {
-            const Word d = decode_word(sp[tile_slot(i)], a.sub);
-            if (d.kind == kPixel) {
-                if (has) {
-                    const int jj = jump_of(last, d.raw, a.jump);
-                    epoch += jj;
-                    fwd += jj > 0;
-                    back += jj < 0;
-                }
-                has = true;
-                last = d.raw;
-                ++npix;
-                if (epoch < 0) {
-                    err |= kErrStream;
-                } else {
-                    tv[j] = d.raw + (uint64_t)epoch * kPixPeriod;
-                    tmax1 = max(tmax1, tv[j] + 1);
-                }
-            } else if (d.kind == kOther) {
-                ++nother;
-            }
-        }
-    }
-
-    // shot of each pixel (latest trigger at or before it), cut, keep
     uint32_t sv[kTileItems];
     uint32_t nkeep = 0, npre = 0, ncut = 0, nlate = 0;
     uint32_t first_s = kNo, last_s = 0;
@@ -342,43 +336,61 @@ __global__ __launch_bounds__(kTileThreads) void k_assign(AssignArgs a) {
 #pragma unroll
     for (int j = 0; j < kTileItems; ++j) {
         sv[j] = kNo;
-        if (tv[j] != ~0ull) {
-            const uint64_t t = tv[j];
-            uint64_t ub, trig;
-            const bool below = s_lo > 0 && t < slice[0];
-            const bool above = has_above && t >= slice[len];
-            if (!below && !above) {
-                // entries before the slice are <= t, entries after it are > t
-                const bool ok = (hint == 0 || slice[hint - 1] <= t) && (hint == len || t < slice[hint]);
-                if (!ok) hint = (uint32_t)upper_bound_u64(slice, 0, len, t);
-                ub = s_lo + hint;
-                trig = hint ? slice[hint - 1] : 0;
+        const uint64_t dv = tv[j];
+        tv[j] = ~0ull;
+        if (dv & kNotPixel) {
+            nother += (dv & kOtherWord) ? 1u : 0u;
+            continue;
+        }
+        const uint64_t raw = dv & (kPixPeriod - 1);
+        if (has) {
+            const int jj = jump_of(last, raw, a.jump);
+            epoch += jj;
+            fwd += jj > 0;
+            back += jj < 0;
+        }
+        has = true;
+        last = raw;
+        ++npix;
+        if (epoch < 0) {
+            err |= kErrStream;
+            continue;
+        }
+        const uint64_t t = raw + (uint64_t)epoch * kPixPeriod;
+        tmax1 = max(tmax1, t + 1);
+        uint64_t ub, trig;
+        const bool below = s_lo > 0 && t < slice[0];
+        const bool above = has_above && t >= slice[len];
+        if (!below && !above) {
+            // entries before the slice are <= t, entries after it are > t
+            const bool ok = (hint == 0 || slice[hint - 1] <= t) && (hint == len || t < slice[hint]);
+            if (!ok) hint = (uint32_t)upper_bound_u64(slice, 0, len, t);
+            ub = s_lo + hint;
+            trig = hint ? slice[hint - 1] : 0;
+        } else {
+            ub = upper_bound_u64(a.tab, 0, n_tab, t);
+            trig = ub ? a.tab[ub - 1] : 0;
+        }
+        if (ub == 0) {
+            if (a.tab_has_before) ++nlate; else ++npre;
+        } else {
+            const uint64_t s = ub - 1;
+            const uint64_t tof = t - trig;
+            if (tof > a.tof_max) {
+                ++ncut;
+            } else if (s < a.first_open) {
+                ++nlate;
             } else {
-                ub = upper_bound_u64(a.tab, 0, n_tab, t);
-                trig = ub ? a.tab[ub - 1] : 0;
-            }
-            tv[j] = ~0ull;
-            if (ub == 0) {
-                if (a.tab_has_before) ++nlate; else ++npre;
-            } else {
-                const uint64_t s = ub - 1;
-                const uint64_t tof = t - trig;
-                if (tof > a.tof_max) {
-                    ++ncut;
-                } else if (s < a.first_open) {
-                    ++nlate;
+                sv[j] = (uint32_t)s;
+                ++nkeep;
+                if (first_s == kNo) first_s = (uint32_t)s;
+                if ((uint32_t)s < last_s) sorted = false;
+                last_s = (uint32_t)s;
+                if constexpr (kSoA) {
+                    tv[j] = t;
                 } else {
-                    sv[j] = (uint32_t)s;
-                    ++nkeep;
-                    if (first_s == kNo) first_s = (uint32_t)s;
-                    if ((uint32_t)s < last_s) sorted = false;
-                    last_s = (uint32_t)s;
-                    if constexpr (kSoA) {
-                        tv[j] = t;
-                    } else {
-                        const Word d = decode_word(sp[tile_slot(threadIdx.x * kTileItems + j)], a.sub);
-                        tv[j] = pack_event(d.x, d.y, d.tot, (uint32_t)tof);
-                    }
+                    tv[j] = pack_event((uint32_t)(dv >> 34) & 255u, (uint32_t)(dv >> 42) & 255u,
+                                       (uint32_t)(dv >> 50) & 1023u, (uint32_t)tof);
                 }
             }
         }
@@ -543,7 +555,7 @@ void launch_tile_summary(const uint64_t* pk, uint64_t n, uint32_t sub, uint64_t 
                          TileAcc* sums, uint64_t* tdc_slot, hipStream_t s) {
     const uint64_t ntiles = (n + kTilePkts - 1) / kTilePkts;
     if (ntiles == 0) return;
-    hipLaunchKernelGGL(k_tile_summary, dim3((unsigned)ntiles), dim3(kTileThreads), 0, s, pk, n,
+    hipLaunchKernelGGL(k_tile_summary, dim3((unsigned)ntiles), dim3(kSumThreads), 0, s, pk, n,
                        sub, jump, sums, tdc_slot);
 }
 
