@@ -88,6 +88,8 @@ def _bind(lib):
     lib.orc_decode.argtypes = [P, S, P, P, P, P, P, P, S, P, P, S, P, P, P]
     lib.orc_cluster.argtypes = [S, P, P, P, P, ctypes.c_uint32, ctypes.c_uint32, P, P]
     lib.orc_centroid.argtypes = [S, P, P, P, P, P, P, P, S, P, P, S, P]
+    lib.orc_local_maxima.argtypes = [S, P, P, P, P, P, ctypes.c_uint32, ctypes.c_uint32, P, S,
+                                     P, P, S, P]
     lib.orc_run.argtypes = [P, S, P, P, S, P, P]
     for f in ("orc_decode_word", "orc_decode", "orc_cluster", "orc_centroid", "orc_run"):
         getattr(lib, f).restype = ctypes.c_int
@@ -181,6 +183,26 @@ class Oracle:
                                    _ptr(hits), max(n, 1), ctypes.byref(nh))
         if rc != OK:
             raise OracleError(rc, "centroid")
+        return hits[:nh.value].copy()
+
+    def local_maxima(self, x, y, tot, shot, toa, trig, dxy=1, dt_ticks=128, walk_ns=None):
+        """The paper's hits: local maxima of ToT over the neighbourhood and
+        Eq. (9) over each one's row of A (see orc_local_maxima)."""
+        x = np.ascontiguousarray(x, np.uint16)
+        y = np.ascontiguousarray(y, np.uint16)
+        tot = np.ascontiguousarray(tot, np.uint16)
+        shot = np.ascontiguousarray(shot, np.uint32)
+        toa = np.ascontiguousarray(toa, np.uint64)
+        trig = np.ascontiguousarray(trig, np.uint64)
+        walk = None if walk_ns is None else np.ascontiguousarray(walk_ns, np.float64)
+        n = x.size
+        hits = np.empty(max(n, 1), HIT_DTYPE)
+        nh = ctypes.c_size_t()
+        rc = self.lib.orc_local_maxima(n, _ptr(x), _ptr(y), _ptr(tot), _ptr(shot), _ptr(toa),
+                                       int(dxy), int(dt_ticks), _ptr(trig), trig.size, _ptr(walk),
+                                       _ptr(hits), max(n, 1), ctypes.byref(nh))
+        if rc != OK:
+            raise OracleError(rc, "local_maxima")
         return hits[:nh.value].copy()
 
     def run(self, packets, **kw):

@@ -31,6 +31,11 @@
  *               Delta ToF(ToT) (Eq. 1) is subtracted from each pixel's ToF.
  *
  * Integer moments are exact (int64); the three divisions are done in double.
+ *
+ * The paper's own hit definition is here too (orc_local_maxima): a pixel is
+ * a hit when its ToT exceeds that of every neighbour (Sec. V, Local Maxima,
+ * Eqs. 6-7), and its centroid is Eq. (9) over its own row of A, i.e. its
+ * direct neighbours, not the closure.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -394,6 +399,102 @@ int orc_centroid(size_t n, const uint16_t* x, const uint16_t* y,
 done:
     free(W); free(Sx); free(Sy); free(St); free(Ux); free(Uy); free(Ut);
     free(Sw); free(Uw); free(cnt); free(tmin); free(roots);
+    return rc;
+}
+
+/* ---------------------------------------------------- paper local maxima */
+/* Sec. V, Local Maxima: with M the row-repeated ToT masked by A (Eq. 6), row
+ * i of M - M^T has maximum 0 exactly when no neighbour of i carries more ToT
+ * (Eq. 7).  The paper breaks ties by adding 0.001 i to the ToT; that is read
+ * here as a tie-break by index: i is a local maximum when every neighbour
+ * j != i has (ToT_j, j) < (ToT_i, i) lexicographically.  Each local maximum
+ * is one hit whose centroid is Eq. (9) over row i of A (its neighbours and
+ * itself): X = sum_j A_ij ToT_j x_j / sum_j A_ij ToT_j, same for Y and ToF.
+ * Written out per shot by brute force over all pairs of its pixels.  Hits in
+ * (shot, index) order; label = index of the local maximum; npix, tot_sum and
+ * toa_first describe its row; a row without ToT gives plain means, flag 1. */
+static int orc_nb(const uint16_t* x, const uint16_t* y, const uint64_t* toa, size_t i,
+                  size_t j, uint32_t r, uint32_t dt)
+{
+    const int64_t dx = (int64_t)x[i] - x[j], dy = (int64_t)y[i] - y[j];
+    const int64_t d = (int64_t)(toa[i] - toa[j]);
+    return (dx < 0 ? -dx : dx) <= r && (dy < 0 ? -dy : dy) <= r && (d < 0 ? -d : d) <= dt;
+}
+
+int orc_local_maxima(size_t n, const uint16_t* x, const uint16_t* y, const uint16_t* tot,
+                     const uint32_t* shot, const uint64_t* toa, uint32_t dxy, uint32_t dt_ticks,
+                     const uint64_t* trig, size_t n_trig, const double* walk_ns, orc_hit* hits,
+                     size_t hit_cap, size_t* n_hits)
+{
+    *n_hits = 0;
+    for (size_t i = 0; i < n; ++i)
+        if (shot[i] >= n_trig) return ORC_EINVAL;
+    size_t* idx = (size_t*)malloc((n ? n : 1) * sizeof(size_t));
+    if (!idx) return ORC_ENOMEM;
+    for (size_t i = 0; i < n; ++i) idx[i] = i;
+    g_root_shot = shot;
+    qsort(idx, n, sizeof(size_t), orc_cmp_root); /* by (shot, index) */
+    size_t nh = 0;
+    int rc = ORC_OK;
+    for (size_t a = 0; a < n;) {
+        size_t b = a;
+        while (b < n && shot[idx[b]] == shot[idx[a]]) ++b;
+        for (size_t p = a; p < b; ++p) {
+            const size_t i = idx[p];
+            int is_max = 1;
+            for (size_t q = a; q < b && is_max; ++q) {
+                const size_t j = idx[q];
+                if (j == i || !orc_nb(x, y, toa, i, j, dxy, dt_ticks)) continue;
+                if (tot[j] > tot[i] || (tot[j] == tot[i] && j > i)) is_max = 0;
+            }
+            if (!is_max) continue;
+            int64_t W = 0, Sx = 0, Sy = 0, St = 0, Ux = 0, Uy = 0, Ut = 0;
+            double Sw = 0, Uw = 0;
+            uint64_t cnt = 0, tmin = UINT64_MAX;
+            for (size_t q = a; q < b; ++q) {
+                const size_t j = idx[q];
+                if (j != i && !orc_nb(x, y, toa, i, j, dxy, dt_ticks)) continue;
+                const int64_t tof = (int64_t)(toa[j] - trig[shot[j]]);
+                W += tot[j];
+                Sx += (int64_t)tot[j] * x[j];
+                Sy += (int64_t)tot[j] * y[j];
+                St += (int64_t)tot[j] * tof;
+                Ux += x[j];
+                Uy += y[j];
+                Ut += tof;
+                if (walk_ns) {
+                    Sw += (double)tot[j] * walk_ns[tot[j] & 1023];
+                    Uw += walk_ns[tot[j] & 1023];
+                }
+                cnt++;
+                if (toa[j] < tmin) tmin = toa[j];
+            }
+            if (nh < hit_cap) {
+                orc_hit* h = &hits[nh];
+                memset(h, 0, sizeof(*h));
+                h->shot = shot[i];
+                h->label = i;
+                h->toa_first = tmin;
+                h->npix = cnt;
+                h->tot_sum = (uint64_t)W;
+                if (W > 0) {
+                    h->x = (double)Sx / (double)W;
+                    h->y = (double)Sy / (double)W;
+                    h->tof_ns = (ORC_TICK_NS * (double)St - Sw) / (double)W;
+                } else {
+                    h->x = (double)Ux / (double)cnt;
+                    h->y = (double)Uy / (double)cnt;
+                    h->tof_ns = (ORC_TICK_NS * (double)Ut - Uw) / (double)cnt;
+                    h->flags |= 1u;
+                }
+            }
+            ++nh;
+        }
+        a = b;
+    }
+    *n_hits = nh;
+    if (nh > hit_cap) rc = ORC_ECAPACITY;
+    free(idx);
     return rc;
 }
 

@@ -10,7 +10,8 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "tpx_oracle.c")
 PINS = ["tests/test_oracle_paper_example.py", "tests/test_oracle_vs_bruteforce.py",
-        "tests/test_oracle_invariants.py", "tests/test_oracle_decode.py"]
+        "tests/test_oracle_invariants.py", "tests/test_oracle_decode.py",
+        "tests/test_oracle_paper_mode.py"]
 
 MUTANTS = {
     "spatial_off_by_one": ("orc_absdiff(x[i], x[j]) <= dxy", "orc_absdiff(x[i], x[j]) < dxy"),
@@ -38,6 +39,14 @@ MUTANTS = {
                                     "h->x = (double)Ux[r] / (double)(cnt[r] + 1);"),
     "hit_order_by_label_only": ("if (g_root_shot[i] != g_root_shot[j])", "if (0)"),
     "wrap_counter_not_counted": ("(*u->n_wraps)++;", ";"),
+    # paper mode (local maxima, Eq. 9 on A)
+    "paper_tie_break_reversed": ("(tot[j] == tot[i] && j > i)", "(tot[j] == tot[i] && j < i)"),
+    "paper_ties_all_maxima": ("if (tot[j] > tot[i] || (tot[j] == tot[i] && j > i)) is_max = 0;",
+                              "if (tot[j] > tot[i]) is_max = 0;"),
+    "paper_row_without_self": ("if (j != i && !orc_nb(x, y, toa, i, j, dxy, dt_ticks)) continue;",
+                               "if (j == i || !orc_nb(x, y, toa, i, j, dxy, dt_ticks)) continue;"),
+    "paper_time_ignored": (" && (d < 0 ? -d : d) <= dt;", ";"),
+    "paper_row_unweighted": ("Sx += (int64_t)tot[j] * x[j];", "Sx += x[j];"),
 }
 
 
