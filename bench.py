@@ -196,6 +196,42 @@ def run_latency(args):
     return out
 
 
+def run_paper_mode(args, wl):
+    """The paper's local-maximum hits (tpx_local_maxima) on the decoded c2
+    events: events resident in HBM, HIP-event timing on the call's stream."""
+    import torch
+
+    import paper_2603_04942_amd as tpx
+
+    pk = torch.from_numpy(wl.packets.view(np.int64)).cuda()
+    ev, trig, _, _ = tpx.decode(pk, params=tpx.make_params(pix_epoch0=wl.pix_epoch0,
+                                                           tdc_epoch0=wl.tdc_epoch0))
+    del pk
+    n = ev["x"].numel()
+    cap = n // 2 + 1024
+    hits = torch.empty((cap, 48), dtype=torch.uint8, device="cuda")
+    ws = tpx.workspace(0, n)
+    for _ in range(2):
+        rc, nh = tpx.local_maxima_raw(ev, trig, hits, cap, ws)
+        if rc != 0:
+            raise tpx.TpxError(rc, "tpx_local_maxima", tpx.load().tpx_last_error().decode())
+    reps = max(1, args.steps // 2)
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record()
+    for _ in range(reps):
+        rc, nh = tpx.local_maxima_raw(ev, trig, hits, cap, ws)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / reps
+    alg = 18 * n + HIT_BYTES * nh
+    return dict(workload="c2 decoded events (SoA in HBM): local maxima of ToT over the 8-neighbourhood "
+                         "within 200 ns, Eq. 9 over each maximum's row",
+                events=int(n), hits=int(nh), ms_per_call=ms, value=n / (ms * 1e-3), unit="events/s",
+                algorithmic_bytes=int(alg), achieved_gbs=alg / (ms * 1e-3) / 1e9,
+                frac=alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS)
+
+
 def run_cpu_baseline(wl, frac):
     import oracle
 
@@ -220,6 +256,7 @@ def main():
     ap.add_argument("--cpu-frac", type=float, default=1.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-latency", action="store_true")
+    ap.add_argument("--no-paper-mode", action="store_true")
     ap.add_argument("--latency-shots", type=int, default=36000)
     ap.add_argument("--latency-chunks", type=int, nargs="+", default=[8192, 131072, 2097152],
                     help="packets per chunk (64 KiB, 1 MiB, 16 MiB)")
@@ -292,6 +329,9 @@ def main():
         "hits_per_s": n_hits / (ms * 1e-3),
         "acquisition_multiple": value / (n_ev / (args.shots * 1e-3)),
     }
+    if not args.no_paper_mode:
+        out["paper_mode"] = run_paper_mode(args, wl)
+        log(f"paper mode: {out['paper_mode']}")
     if not args.no_latency:
         out["stream_latency"] = run_latency(args)
         log(f"latency: {out['stream_latency']}")

@@ -117,9 +117,10 @@ typedef struct {
 
 void tpx_unwrap_state_init(tpx_unwrap_state* st_h, const tpx_params* p_h);
 
-/* Device workspace needed by tpx_decode / tpx_cluster / tpx_centroid for up
- * to max_packets packets or max_events events.  The workspace holds only
- * transient data; its contents need not be preserved between calls. */
+/* Device workspace needed by tpx_decode / tpx_cluster / tpx_centroid /
+ * tpx_local_maxima for up to max_packets packets or max_events events.  The
+ * workspace holds only transient data; its contents need not be preserved
+ * between calls. */
 size_t tpx_workspace_bytes(size_t max_packets, size_t max_events);
 
 /* Decode, unwrap and assign (Sec. III; Sec. IV, ToA Unwrapping and
@@ -148,6 +149,29 @@ tpx_status tpx_decode(const uint64_t* pkts, size_t n_pkts, const tpx_params* p_h
 tpx_status tpx_cluster(tpx_events ev, size_t n_ev, const tpx_params* p_h,
                        uint32_t* labels, size_t* n_clusters_h, void* ws,
                        size_t ws_bytes, void* stream);
+
+/* The paper's own hits (Sec. V, Local Maxima and Centroiding; Eqs. 6-7 and
+ * Eq. 9 on A itself), event mode.  Event i is a hit when no neighbour (same
+ * shot, |dx| <= dxy, |dy| <= dxy, |ToA difference| <= dt_ticks) carries more
+ * ToT; between equal ToT the later event wins (the paper's +0.001 i tie-break,
+ * read as a tie-break by index).  Its centroid is Eq. (9) over itself and its
+ * direct neighbours (not the transitive closure): x = sum(ToT x) / sum(ToT),
+ * the same for y and ToF = ToA - trig_toa[shot] (minus walk_lut_ns[ToT] when
+ * given); a row without ToT gives plain means and flag bit 0.
+ *   ev, n_ev      device SoA events (any order; shots need not be sorted)
+ *   trig_toa      device u64[n_trig], trigger time of every shot value
+ *   hits          device tpx_hit[hit_cap], written in (shot, index) order;
+ *                 label = event index of the maximum, npix / tot_sum /
+ *                 toa_first describe its row
+ *   n_hits_h      host: number of hits (also on TPX_ECAPACITY)
+ *   ws, ws_bytes  device workspace of at least tpx_workspace_bytes(0, n_ev)
+ * Errors: TPX_EINVAL (NULL pointers, x or y > 255, ToT > 1023, a shot value
+ * >= n_trig), TPX_ECAPACITY (hit_cap too small, or a group of shots that
+ * does not fit one 2,048-event segment: shots of up to 1,536 events always
+ * fit).  Synchronises the stream. */
+tpx_status tpx_local_maxima(tpx_events ev, size_t n_ev, const uint64_t* trig_toa, size_t n_trig,
+                            const tpx_params* p, tpx_hit* hits, size_t hit_cap, size_t* n_hits_h,
+                            void* ws, size_t ws_bytes, void* stream);
 
 /* ToT-weighted centroids (Sec. V, Centroiding, Eqs. 8-9) of the hits given by
  * `labels` (as produced by tpx_cluster: labels[i] is the smallest index of i's

@@ -64,7 +64,8 @@ HIT_DTYPE = np.dtype([("x", "<f4"), ("y", "<f4"), ("tof_ns", "<f4"), ("npix", "<
 assert HIT_DTYPE.itemsize == 48
 
 EXPORTS = ("tpx_params_default", "tpx_unwrap_state_init", "tpx_workspace_bytes", "tpx_decode",
-           "tpx_cluster", "tpx_centroid", "tpx_stream_create", "tpx_process_stream",
+           "tpx_cluster", "tpx_centroid", "tpx_local_maxima", "tpx_stream_create",
+           "tpx_process_stream",
            "tpx_stream_get_state", "tpx_stream_set_state", "tpx_stream_destroy",
            "tpx_status_str", "tpx_last_error", "tpx_stream_fallback_count",
            "tpx_stream_set_timing", "tpx_stream_get_timing", "tpx_stream_stage_name")
@@ -90,6 +91,7 @@ def load(path=LIB_PATH):
     lib.tpx_decode.argtypes = [P, S, P, P, Events, S, P, S, P, P, P, P, S, P]
     lib.tpx_cluster.argtypes = [Events, S, P, P, P, P, S, P]
     lib.tpx_centroid.argtypes = [Events, P, S, P, S, P, P, S, P, P, S, P]
+    lib.tpx_local_maxima.argtypes = [Events, S, P, S, P, P, S, P, P, S, P]
     lib.tpx_stream_create.argtypes = [P, S, P]
     lib.tpx_process_stream.argtypes = [P, P, S, ctypes.c_int, P, S, P, P, P]
     lib.tpx_stream_get_state.argtypes = [P, P, P]
@@ -252,6 +254,40 @@ def centroid(ev, labels, trig, params=None, hit_cap=None, ws=None):
         raise TpxError(rc, "tpx_centroid", f"need {nh.value} hits")
     _check(rc, "tpx_centroid")
     return hits_to_numpy(hits, nh.value)
+
+
+def local_maxima(ev, trig, params=None, hit_cap=None, ws=None):
+    """tpx_local_maxima (the paper's local-maximum hits): numpy structured
+    array of hits (HIT_DTYPE)."""
+    torch = _torch()
+    lib = load()
+    n = ev["x"].numel()
+    p = params or make_params()
+    trig = _u64(torch, trig)
+    hit_cap = n if hit_cap is None else hit_cap
+    hits = torch.empty((max(hit_cap, 1), 48), dtype=torch.uint8, device="cuda")
+    ws = workspace(0, n) if ws is None else ws
+    nh = ctypes.c_size_t()
+    rc = lib.tpx_local_maxima(events_struct(ev), n, _ptr(trig), trig.numel(), ctypes.byref(p),
+                              _ptr(hits), hit_cap, ctypes.byref(nh), _ptr(ws), ws.numel(),
+                              _stream(torch))
+    if rc == ECAPACITY:
+        raise TpxError(rc, "tpx_local_maxima", f"need {nh.value} hits or smaller shot groups")
+    _check(rc, "tpx_local_maxima")
+    return hits_to_numpy(hits, nh.value)
+
+
+def local_maxima_raw(ev, trig, hits, hit_cap, ws, params=None):
+    """Device-only tpx_local_maxima into a caller's hit buffer; returns
+    (status, n_hits) without copying anything back."""
+    torch = _torch()
+    lib = load()
+    p = params or make_params()
+    nh = ctypes.c_size_t()
+    rc = lib.tpx_local_maxima(events_struct(ev), ev["x"].numel(), _ptr(trig), trig.numel(),
+                              ctypes.byref(p), _ptr(hits), hit_cap, ctypes.byref(nh), _ptr(ws),
+                              ws.numel(), _stream(torch))
+    return rc, int(nh.value)
 
 
 class Stream:

@@ -32,6 +32,8 @@ tpx_status fail(tpx_status st, const char* fmt, ...) {
     } while (0)
 
 constexpr uint32_t kQ = 1024;           // segment stride (events)
+constexpr uint32_t kQPaper = 512;       // segment stride of the paper mode: a shot of up to
+                                        // 1,536 events always fits one 2,048-event segment
 constexpr int kStages = 7;              // timed stages of the stream fast path
 constexpr uint64_t kMaxEvents = 0xFFFFFFF0ull;
 // packets in one decode call: the tile look-back keeps a kept-event count and a
@@ -94,7 +96,7 @@ DecodeWs carve_decode(Carve& c, uint64_t n) {
 struct ClusterWs {
     DevResults* res;
     uint32_t *flags, *scan, *block_tmp, *keys, *vals, *keys2, *vals2, *grp_off, *grp_shot;
-    uint32_t* seg_lo;
+    uint32_t *seg_lo, *seg_cnt, *seg_off;
     uint64_t* lb;
     uint32_t* big[6];
     uint64_t* acc;
@@ -111,7 +113,9 @@ ClusterWs carve_cluster(Carve& c, uint64_t m, bool with_acc) {
     w.vals2 = c.take<uint32_t>(m + 1);
     w.grp_off = c.take<uint32_t>(m + 2);
     w.grp_shot = c.take<uint32_t>(m + 1);
-    w.seg_lo = c.take<uint32_t>(m / kQ + 4);
+    w.seg_lo = c.take<uint32_t>(m / kQPaper + 4);
+    w.seg_cnt = c.take<uint32_t>(m / kQPaper + 4);
+    w.seg_off = c.take<uint32_t>(m / kQPaper + 5);
     w.lb = c.take<uint64_t>(m / kQ + 4);
     for (int k = 0; k < 6; ++k) w.big[k] = c.take<uint32_t>(m + 1);
     w.acc = with_acc ? c.take<uint64_t>(10 * (m + 1)) : nullptr;
@@ -363,6 +367,74 @@ tpx_status tpx_cluster(tpx_events ev, size_t n_ev, const tpx_params* p_h, uint32
     if ((rc = read_res(w.res, &r, s))) return rc;
     if ((rc = res_error(r))) return rc;
     if (n_clusters_h) *n_clusters_h = r.n_hits;
+    return TPX_OK;
+}
+
+tpx_status tpx_local_maxima(tpx_events ev, size_t n_ev, const uint64_t* trig_toa, size_t n_trig,
+                            const tpx_params* p_h, tpx_hit* hits, size_t hit_cap,
+                            size_t* n_hits_h, void* ws, size_t ws_bytes, void* stream) {
+    tpx_status rc = check_params(p_h);
+    if (rc) return rc;
+    if (!n_hits_h) return fail(TPX_EINVAL, "n_hits_h is NULL");
+    if (n_ev >= kMaxEvents) return fail(TPX_EINVAL, "too many events");
+    if (n_ev && (!ev.x || !ev.y || !ev.shot || !ev.toa || !ev.tot || !trig_toa))
+        return fail(TPX_EINVAL, "an input array is NULL");
+    if (hit_cap && !hits) return fail(TPX_EINVAL, "hits is NULL");
+    if (!ws || ws_bytes < tpx_workspace_bytes(0, n_ev))
+        return fail(TPX_EINVAL, "workspace too small (need %zu bytes)", tpx_workspace_bytes(0, n_ev));
+    *n_hits_h = 0;
+    if (n_ev == 0) return TPX_OK;
+    hipStream_t s = (hipStream_t)stream;
+    Carve c{(uintptr_t)ws, 0};
+    ClusterWs w = carve_cluster(c, n_ev, false);
+    zero_res(w.res, s);
+    launch_fill_u64((uint64_t*)&w.res->n_in, n_ev, 1, s);
+    launch_check_events(ev, n_ev, w.res, s);
+    DevResults r;
+    if ((rc = read_res(w.res, &r, s))) return rc;
+    if ((rc = res_error(r))) return rc;
+    if (r.max_key >= n_trig) return fail(TPX_EINVAL, "shot %llu has no trigger time", r.max_key);
+    const uint32_t* sorted_key = ev.shot;
+    const uint32_t* perm = nullptr;
+    if (r.unsorted) {
+        launch_iota_u32(w.vals, n_ev, s);
+        HIPCHK(hipMemcpyAsync(w.keys, ev.shot, n_ev * 4, hipMemcpyDeviceToDevice, s));
+        uint32_t *ko, *vo;
+        radix_sort_pairs(w.keys, w.vals, w.keys2, w.vals2, w.flags, w.scan, w.block_tmp, n_ev,
+                         bits_for(r.max_key), s, &ko, &vo);
+        sorted_key = ko;
+        perm = vo;
+    }
+    launch_boundaries(sorted_key, n_ev, w.flags, w.scan, w.block_tmp, w.grp_off, w.grp_shot, w.res, s);
+    ClusterArgs a{};
+    a.soa = ev;
+    a.perm = perm;
+    a.grp_off = w.grp_off;
+    a.grp_shot = w.grp_shot;
+    a.n_ev_dev = &w.res->n_in;
+    a.n_grp_dev = &w.res->n_groups;
+    a.seg_lo = w.seg_lo;
+    a.seg_cnt = w.seg_cnt;
+    a.seg_off = w.seg_off;
+    a.q = kQPaper;
+    a.dxy = p_h->dxy;
+    a.dt = p_h->dt_ticks;
+    a.walk = p_h->walk_lut_ns;
+    a.hits = hits;
+    a.hit_cap = hit_cap;
+    a.res = w.res;
+    launch_seg_table(w.grp_off, a.n_grp_dev, a.n_ev_dev, nullptr, kQPaper, n_ev, w.seg_lo, w.res,
+                     s);
+    const uint64_t grid = cluster_grid(n_ev, kQPaper);
+    launch_paper(a, trig_toa, false, grid, s);
+    launch_scan_u32(w.seg_cnt, w.seg_off, 0, &w.res->n_seg, w.block_tmp, s);
+    launch_paper(a, trig_toa, true, grid, s);
+    if ((rc = read_res(w.res, &r, s))) return rc;
+    if (r.err & kErrCapacity)
+        return fail(TPX_ECAPACITY, "a shot group does not fit one %d-event segment", cluster_capacity());
+    if ((rc = res_error(r))) return rc;
+    *n_hits_h = r.n_hits;
+    if (r.n_hits > hit_cap) return fail(TPX_ECAPACITY, "need %llu hit slots", r.n_hits);
     return TPX_OK;
 }
 

@@ -883,4 +883,175 @@ void launch_seg_centroid(const ClusterArgs& a, uint64_t grid, hipStream_t s) {
     hipLaunchKernelGGL(k_seg_centroid, dim3((unsigned)grid), dim3(kCWG), 0, s, a);
 }
 
+// ------------------------------------------------- paper local maxima
+// The paper's own hits (Sec. V, Local Maxima and Centroiding): event i is a
+// hit when no neighbour carries more ToT (Eqs. 6-7), ties going to the later
+// event (its +0.001 i read as a tie-break by position), and its centroid is
+// Eq. (9) over row i of A: itself and its direct neighbours.  Event mode, one
+// workgroup per segment on the same image as k_cluster; the kernel runs
+// twice: counting the maxima of every segment, then (after a prefix sum over
+// segments) writing each maximum's hit at seg_off[k] + its rank.
+// LDS byte layout of k_paper: image, then per event the packed word, the
+// chain head and link, and the ToT
+constexpr int kPOffEv = 32768;         // u64[kCap]
+constexpr int kPOffChn = 49152;        // u32[kCap]
+constexpr int kPOffNxt = 57344;        // u16[kCap]
+constexpr int kPOffTot = 61440;        // u16[kCap]
+constexpr int kLdsPaper = 65536;
+static_assert(kPOffTot + 2 * kCap <= kLdsPaper, "paper layout");
+
+template <bool kWrite>
+__global__ __launch_bounds__(kWG) void k_paper(ClusterArgs a, const uint64_t* __restrict__ trig) {
+    __shared__ __attribute__((aligned(16))) uint8_t lds[kLdsPaper];
+    __shared__ uint32_t scan_tmp[kWG / 64 + 1];
+    __shared__ uint32_t goff[kWG + 1];
+    uint16_t* img = (uint16_t*)(lds + kOffImg);
+    uint64_t* evs = (uint64_t*)(lds + kPOffEv);
+    uint32_t* chn = (uint32_t*)(lds + kPOffChn);
+    uint16_t* nxt = (uint16_t*)(lds + kPOffNxt);
+    uint16_t* tt = (uint16_t*)(lds + kPOffTot);
+    const int tid = threadIdx.x;
+    const uint32_t k = blockIdx.x;
+    const uint64_t N = n_events(a);
+    const uint64_t n_seg = (N + a.q - 1) / a.q;
+    if (k >= n_seg) return;
+    Seg sg;
+    if (!seg_bounds(a, k, N, sg)) return;
+    const uint32_t n = sg.n;
+    if (n == 0 || n > (uint32_t)kCap) {
+        if (tid == 0) {
+            if (!kWrite) a.seg_cnt[k] = 0;
+            if (n > (uint32_t)kCap) atomicOr(&a.res->err, (unsigned long long)kErrCapacity);
+        }
+        return;
+    }
+    const uint64_t e0 = sg.e0;
+    const int r = (int)a.dxy;
+    const uint32_t dt = a.dt;
+    unsigned long long* err = &a.res->err;
+    const uint32_t ng = sg.g_hi - sg.g_lo;
+    const bool goff_lds = ng <= (uint32_t)kWG;
+    if (goff_lds) {
+        for (uint32_t i = tid; i <= ng; i += kWG) goff[i] = a.grp_off[sg.g_lo + i];
+    }
+    {
+        uint4* v = (uint4*)img;
+        for (int i = tid; i < kH * 2 / 16; i += kWG) v[i] = make_uint4(~0u, ~0u, ~0u, ~0u);
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < n; i += kWG) {
+        const uint32_t p = (uint32_t)(e0 + i);
+        const uint32_t g = goff_lds ? sg.g_lo + group_of(goff, 0, ng, p)
+                                    : group_of(a.grp_off, sg.g_lo, sg.g_hi, p);
+        evs[i] = pack_lds(load_event<true>(a, e0 + i, g, e0, err));
+        tt[i] = a.soa.tot[orig_of(a, e0 + i)];
+        chn[i] = kNone32;
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < n; i += kWG) {
+        const uint64_t v = evs[i];
+        img[slot_of((uint32_t)v & 255u, (uint32_t)(v >> 8) & 255u)] = (uint16_t)i;
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < n; i += kWG) {
+        const uint64_t v = evs[i];
+        const uint32_t w = img[slot_of((uint32_t)v & 255u, (uint32_t)(v >> 8) & 255u)];
+        if (w != i) {
+            const uint32_t old = atomicExch(&chn[w], i);
+            nxt[i] = (uint16_t)(old == kNone32 ? kNone16 : old);
+        }
+    }
+    __syncthreads();
+    // maxima in position order, one workgroup-wide round at a time
+    bool ok = true;
+    uint32_t running = 0;
+    const uint32_t rounds = (n + kWG - 1) / kWG;
+    for (uint32_t rd = 0; rd < rounds; ++rd) {
+        const uint32_t i = rd * kWG + tid;
+        bool is_max = false;
+        uint64_t v = 0;
+        if (i < n) {
+            v = evs[i];
+            const uint32_t ti = tt[i];
+            is_max = true;
+            ok &= box_events<0>(img, chn, nxt, i, (int)(v & 255u), (int)((v >> 8) & 255u), r, n,
+                                [&](uint32_t j, bool) {
+                                    if (!is_edge(v, evs[j], r, dt)) return;
+                                    const uint32_t tj = tt[j];
+                                    if (tj > ti || (tj == ti && j > i)) is_max = false;
+                                });
+        }
+        uint32_t tot_r;
+        const uint32_t rk = running + wg_flag_scan<kWG>(is_max, scan_tmp, &tot_r);
+        if (kWrite && is_max) {
+            // Eq. (9) over row i of A, exact integer moments
+            const uint64_t oi = orig_of(a, e0 + i);
+            const uint32_t sh = a.soa.shot[oi];
+            const uint64_t T = trig[sh];
+            uint64_t W = 0, cnt = 0, tmin = ~0ull;
+            int64_t Sx = 0, Sy = 0, St = 0, Ux = 0, Uy = 0, Ut = 0;
+            double Sw = 0.0, Uw = 0.0;
+            auto add = [&](uint32_t j) {
+                const uint64_t o = orig_of(a, e0 + j);
+                const uint64_t toa = a.soa.toa[o];
+                const uint64_t vj = evs[j];
+                const int64_t x = (int64_t)(vj & 255u), y = (int64_t)((vj >> 8) & 255u);
+                const int64_t w = tt[j], tof = (int64_t)(toa - T);
+                W += (uint64_t)w;
+                Sx += w * x;
+                Sy += w * y;
+                St += w * tof;
+                Ux += x;
+                Uy += y;
+                Ut += tof;
+                if (a.walk) {
+                    const double wk = (double)a.walk[w & 1023];
+                    Sw += (double)w * wk;
+                    Uw += wk;
+                }
+                ++cnt;
+                tmin = toa < tmin ? toa : tmin;
+            };
+            add(i);
+            ok &= box_events<0>(img, chn, nxt, i, (int)(v & 255u), (int)((v >> 8) & 255u), r, n,
+                                [&](uint32_t j, bool) {
+                                    if (is_edge(v, evs[j], r, dt)) add(j);
+                                });
+            const uint64_t h = a.seg_off[k] + rk;
+            if (h < a.hit_cap) {
+                tpx_hit o;
+                if (W) {
+                    o.x = (float)((double)Sx / (double)W);
+                    o.y = (float)((double)Sy / (double)W);
+                    o.tof_ns = (float)((1.5625 * (double)St - Sw) / (double)W);
+                } else {
+                    o.x = (float)((double)Ux / (double)cnt);
+                    o.y = (float)((double)Uy / (double)cnt);
+                    o.tof_ns = (float)((1.5625 * (double)Ut - Uw) / (double)cnt);
+                }
+                o.npix = (uint32_t)cnt;
+                o.shot = sh;
+                o.label = oi;
+                o.toa_first = tmin;
+                o.tot_sum = (uint32_t)W;
+                o.flags = W ? 0u : 1u;
+                a.hits[h] = o;
+            }
+        }
+        running += tot_r;
+    }
+    if (!ok) atomicOr(err, (unsigned long long)kErrLoopChain);
+    if (!kWrite && tid == 0) a.seg_cnt[k] = running;
+    if (kWrite && k == 0 && tid == 0) a.res->n_hits = a.seg_off[n_seg];
+}
+
+void launch_paper(const ClusterArgs& a, const uint64_t* trig, bool write, uint64_t grid,
+                  hipStream_t s) {
+    if (grid == 0) return;
+    if (write)
+        hipLaunchKernelGGL(k_paper<true>, dim3((unsigned)grid), dim3(kWG), 0, s, a, trig);
+    else
+        hipLaunchKernelGGL(k_paper<false>, dim3((unsigned)grid), dim3(kWG), 0, s, a, trig);
+}
+
 }  // namespace tpx

@@ -81,6 +81,10 @@ void launch_seg_table(const uint32_t* grp_off, const unsigned long long* n_grp_d
                       hipStream_t s);
 // stream mode: moments and hits of the components found by launch_cluster
 void launch_seg_centroid(const ClusterArgs& a, uint64_t grid, hipStream_t s);
+// event mode, the paper's local-maximum hits: count pass (write = false,
+// fills seg_cnt), then write pass (hits at seg_off[k] + rank)
+void launch_paper(const ClusterArgs& a, const uint64_t* trig, bool write, uint64_t grid,
+                  hipStream_t s);
 // workgroups needed to cover every segment of up to max_events events
 uint64_t cluster_grid(uint64_t max_events, uint32_t q);
 int cluster_capacity();

@@ -46,3 +46,28 @@ def test_stream_full_size(tpx, orc, name):
     assert_hits_match(h, ref)
     # conservation over the whole stream
     assert int(h["npix"].astype(np.int64).sum()) == st["n_events"]
+
+
+def test_paper_mode_full_size_sampled(tpx, orc):
+    """tpx_local_maxima over the whole decoded c2 stream (the configuration
+    the benchmark times); the oracle recomputes 250 randomly drawn shots one
+    by one and their hits must match those of the full run."""
+    workers = min(16, os.cpu_count() or 1)
+    w = synth.make_config("c2", with_truth=False, workers=workers)
+    kw = dict(pix_epoch0=w.pix_epoch0, tdc_epoch0=w.tdc_epoch0)
+    ev, trig, _, _ = tpx.decode(w.packets, params=tpx.make_params(**kw))
+    h = tpx.local_maxima(ev, trig)
+    print(f"c2 paper mode: {h.size} hits from {ev['x'].numel()} events", flush=True)
+    shot = ev["shot"].cpu().numpy().view(np.uint32)
+    host = {k: v.cpu().numpy() for k, v in ev.items()}
+    trig_h = trig.cpu().numpy().view(np.uint64)
+    picks = np.sort(np.random.default_rng(2603).choice(int(shot.max()) + 1, 250, replace=False))
+    for s in picks:
+        idx = np.nonzero(shot == s)[0]
+        e = dict(x=host["x"][idx].view(np.uint16), y=host["y"][idx].view(np.uint16),
+                 tot=host["tot"][idx].view(np.uint16), shot=shot[idx],
+                 toa=host["toa"][idx].view(np.uint64))
+        ref = orc.local_maxima(e["x"], e["y"], e["tot"], e["shot"], e["toa"], trig_h)
+        ref["label"] = idx[ref["label"].astype(np.int64)]
+        got = h[h["shot"] == s]
+        assert_hits_match(got, ref)
