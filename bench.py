@@ -190,10 +190,62 @@ def run_latency(args):
             lat_p, _, _ = replay(lim, speed)
             row["paced"][f"{speed:g}x"] = dict(chunks=lim, p50_ms=float(np.percentile(lat_p, 50)),
                                                p99_ms=float(np.percentile(lat_p, 99)))
-        out["sizes"].append(row)
         s.close()
         del hits
+        row["paced_batched"] = batched_replays(args, tpx, w, pk, chunk, pk_rate)
+        out["sizes"].append(row)
     return out
+
+
+def batched_replays(args, tpx, w, pk, chunk, pk_rate):
+    """Paced replays through tpx_service: chunk k is admitted when released;
+    each run takes every chunk admitted so far (up to the batch limit), so
+    when chunks arrive faster than one call per chunk can finish, several go
+    into one call.  Latency of a chunk = completion of its run - release."""
+    import torch
+
+    n_pk = pk.numel()
+    starts = list(range(0, n_pk, chunk))
+    max_batch = max(1 << 19, 4 * chunk)
+    cap = 2 * max_batch
+    hits = torch.empty((cap, 48), dtype=torch.uint8, device="cuda")
+    res = {"max_batch_packets": max_batch}
+    for speed in args.latency_speeds:
+        lim = max(1, min(len(starts), int(2.0 * pk_rate * speed / chunk)))
+        sv = tpx.Service(max_batch, pix_epoch0=w.pix_epoch0, tdc_epoch0=w.tdc_epoch0)
+        t0 = time.perf_counter()
+        rel = [t0 + min(a + chunk, n_pk) / pk_rate / speed for a in starts[:lim]]
+        nxt = done = runs = 0
+        pending, lat = [], []
+        while done < lim:
+            if nxt < lim and not pending:
+                while time.perf_counter() < rel[nxt]:
+                    pass
+            while nxt < lim and time.perf_counter() >= rel[nxt]:
+                a = starts[nxt]
+                rc = sv.lib.tpx_service_submit(sv.h, tpx._ptr(pk[a:a + chunk]),
+                                               min(chunk, n_pk - a), 1, None,
+                                               tpx._stream(torch))
+                if rc == tpx.ECAPACITY:
+                    break
+                if rc != 0:
+                    raise tpx.TpxError(rc, "tpx_service_submit", sv.lib.tpx_last_error().decode())
+                pending.append(rel[nxt])
+                nxt += 1
+            rc, nh, nd, st = sv.run_raw(nxt == lim, hits, cap)
+            t = time.perf_counter()
+            if rc != 0:
+                raise tpx.TpxError(rc, "tpx_service_run", sv.lib.tpx_last_error().decode())
+            k = nd - done
+            lat += [(t - r) * 1e3 for r in pending[:k]]
+            pending = pending[k:]
+            done = nd
+            runs += 1
+        sv.close()
+        res[f"{speed:g}x"] = dict(chunks=lim, runs=runs, p50_ms=float(np.percentile(lat, 50)),
+                                  p99_ms=float(np.percentile(lat, 99)))
+    del hits
+    return res
 
 
 def run_paper_mode(args, wl):

@@ -221,6 +221,39 @@ tpx_status tpx_stream_get_timing(const tpx_stream* s, float* ms_h, size_t n,
                                  size_t* n_stages_h);
 const char* tpx_stream_stage_name(size_t i);
 
+/* Continuous batching over one stream (the streaming workload's chunked
+ * acquisition, Sec. IV: the unwrap runs across the whole stream).  Chunks are
+ * admitted into a device ring as they arrive; every run processes all whole
+ * chunks admitted so far, up to max_batch_pkts packets, as one
+ * tpx_process_stream call.  Because the stream path gives the same hits for
+ * any split of the stream into chunks, batching changes only when hits
+ * appear, never what they are.
+ *   tpx_service_create  max_batch_pkts: largest batch (and chunk); ring_pkts
+ *                       >= max_batch_pkts: admission capacity.  Allocates the
+ *                       ring, a staging buffer and a tpx_stream.
+ *   tpx_service_submit  copies n_pkts words (device memory when
+ *                       chunk_on_device, else host) into the ring,
+ *                       asynchronously on `stream`; *seq_h = the chunk's
+ *                       number (0, 1, ...).  TPX_EINVAL when n_pkts >
+ *                       max_batch_pkts, TPX_ECAPACITY when the ring is full
+ *                       (run first); the service is then unchanged.
+ *   tpx_service_run     one batch: hits of the shots it closes (all shots when
+ *                       flush and the batch holds every admitted chunk) as in
+ *                       tpx_process_stream; *n_done_h = chunks processed so
+ *                       far.  With nothing admitted it still flushes.  On an
+ *                       error the batch stays admitted.  Synchronises
+ *                       `stream`.
+ * Calls on one service must not overlap. */
+typedef struct tpx_service tpx_service;
+tpx_status tpx_service_create(const tpx_params* p_h, size_t max_batch_pkts, size_t ring_pkts,
+                              tpx_service** out_h);
+tpx_status tpx_service_submit(tpx_service* sv, const uint64_t* chunk, size_t n_pkts,
+                              int chunk_on_device, uint64_t* seq_h, void* stream);
+tpx_status tpx_service_run(tpx_service* sv, int flush, tpx_hit* hits, size_t hit_cap,
+                           size_t* n_hits_h, uint64_t* n_done_h, tpx_stats* stats_h,
+                           void* stream);
+void tpx_service_destroy(tpx_service* sv);
+
 const char* tpx_status_str(tpx_status st);
 const char* tpx_last_error(void); /* thread-local detail of the last failure */
 

@@ -68,7 +68,8 @@ EXPORTS = ("tpx_params_default", "tpx_unwrap_state_init", "tpx_workspace_bytes",
            "tpx_process_stream",
            "tpx_stream_get_state", "tpx_stream_set_state", "tpx_stream_destroy",
            "tpx_status_str", "tpx_last_error", "tpx_stream_fallback_count",
-           "tpx_stream_set_timing", "tpx_stream_get_timing", "tpx_stream_stage_name")
+           "tpx_stream_set_timing", "tpx_stream_get_timing", "tpx_stream_stage_name",
+           "tpx_service_create", "tpx_service_submit", "tpx_service_run", "tpx_service_destroy")
 
 _lib = None
 
@@ -93,6 +94,11 @@ def load(path=LIB_PATH):
     lib.tpx_centroid.argtypes = [Events, P, S, P, S, P, P, S, P, P, S, P]
     lib.tpx_local_maxima.argtypes = [Events, S, P, S, P, P, S, P, P, S, P]
     lib.tpx_stream_create.argtypes = [P, S, P]
+    lib.tpx_service_create.argtypes = [P, S, S, P]
+    lib.tpx_service_submit.argtypes = [P, P, S, ctypes.c_int, P, P]
+    lib.tpx_service_run.argtypes = [P, ctypes.c_int, P, S, P, P, P, P]
+    lib.tpx_service_destroy.argtypes = [P]
+    lib.tpx_service_destroy.restype = None
     lib.tpx_process_stream.argtypes = [P, P, S, ctypes.c_int, P, S, P, P, P]
     lib.tpx_stream_get_state.argtypes = [P, P, P]
     lib.tpx_stream_set_state.argtypes = [P, P, S]
@@ -363,6 +369,61 @@ class Stream:
     @property
     def fallback_count(self):
         return int(self.lib.tpx_stream_fallback_count(self.h))
+
+
+class Service:
+    """tpx_service: continuous batching of chunks over one stream."""
+
+    def __init__(self, max_batch_pkts, ring_pkts=None, params=None, **kw):
+        self.torch = _torch()
+        self.lib = load()
+        self.p = params or make_params(**kw)
+        self.h = ctypes.c_void_p()
+        ring = 4 * max_batch_pkts if ring_pkts is None else ring_pkts
+        _check(self.lib.tpx_service_create(ctypes.byref(self.p), max_batch_pkts, ring,
+                                           ctypes.byref(self.h)), "tpx_service_create")
+
+    def submit(self, chunk):
+        """Admit a chunk (device tensor or numpy uint64); returns its number."""
+        torch = self.torch
+        if isinstance(chunk, np.ndarray):
+            arr = np.ascontiguousarray(chunk.view(np.uint64))
+            ptr, n, dev = arr.ctypes.data, arr.size, 0
+        else:
+            arr = chunk
+            ptr, n, dev = arr.data_ptr(), arr.numel(), 1
+        seq = ctypes.c_uint64()
+        rc = self.lib.tpx_service_submit(self.h, ctypes.c_void_p(ptr), n, dev, ctypes.byref(seq),
+                                         _stream(torch))
+        _check(rc, "tpx_service_submit")
+        return int(seq.value)
+
+    def run_raw(self, flush, hits, hit_cap):
+        """One batch into a device hit buffer: (status, n_hits, n_done, stats)."""
+        nh, nd = ctypes.c_size_t(), ctypes.c_uint64()
+        st = Stats()
+        rc = self.lib.tpx_service_run(self.h, int(flush), _ptr(hits), hit_cap, ctypes.byref(nh),
+                                      ctypes.byref(nd), ctypes.byref(st), _stream(self.torch))
+        return rc, int(nh.value), int(nd.value), st
+
+    def run(self, flush=False, hit_cap=1 << 20):
+        hits = self.torch.empty((max(hit_cap, 1), 48), dtype=self.torch.uint8, device="cuda")
+        rc, n, nd, st = self.run_raw(flush, hits, hit_cap)
+        if rc == ECAPACITY:
+            raise TpxError(rc, "tpx_service_run", f"need {n} hits")
+        _check(rc, "tpx_service_run")
+        return hits_to_numpy(hits, n), nd, st.as_dict()
+
+    def close(self):
+        if self.h:
+            self.lib.tpx_service_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def process_stream(packets, flush=True, **kw):

@@ -25,6 +25,13 @@ tpx_status fail(tpx_status st, const char* fmt, ...) {
     return st;
 }
 
+}  // namespace
+
+// error text for the other translation units of the library
+tpx_status tpx::report(tpx_status st, const char* msg) { return fail(st, "%s", msg); }
+
+namespace {
+
 #define HIPCHK(x)                                                                         \
     do {                                                                                  \
         hipError_t e_ = (x);                                                              \

@@ -89,6 +89,9 @@ void launch_paper(const ClusterArgs& a, const uint64_t* trig, bool write, uint64
 uint64_t cluster_grid(uint64_t max_events, uint32_t q);
 int cluster_capacity();
 
+// sets the text returned by tpx_last_error and returns st (tpx_api.hip)
+tpx_status report(tpx_status st, const char* msg);
+
 // utilities (tpx_util.hip)
 void launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
 void launch_fill_u32_dev(uint32_t* p, uint32_t v, uint64_t base, const unsigned long long* n_dev,
