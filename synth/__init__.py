@@ -4,3 +4,4 @@ from .vmi import (GRID, KIND_OTHER, KIND_PIXEL, KIND_TRIGGER, PIX_WRAP_TICKS,  #
                   SHOT_PERIOD_TICKS, SPECS, TDC_WRAP_TICKS, TICK_NS, TRIG_SUBTYPE,
                   Spec, Workload, encode_pixels, encode_tdc, generate, make_config,
                   tiny_events)
+from .clusters import init_mlp_params, make_clusters  # noqa: F401,E402
