@@ -248,6 +248,89 @@ def batched_replays(args, tpx, w, pk, chunk, pk_rate):
     return res
 
 
+def _cluster_block(job):
+    import synth
+    seed, b, n = job
+    return synth.make_clusters(seed, n, block=n, first_block=b)
+
+
+def run_learned(args, pool, plain_hits_per_s):
+    """The learned centroider / multiplicity splitter: trained from scratch
+    on generated clusters (30 % overlapping pairs, sigma 0.5-2.5, the same
+    time-walk model), streamed from the worker pool in blocks; scored on
+    held-out clusters against the weighted centroid; inference (patches,
+    forward, refine) timed with HIP events on the calls' stream."""
+    import torch
+
+    import paper_2603_04942_amd as tpx
+    import paper_2603_04942_amd.learned as LR
+    import synth
+
+    blk = args.learned_block
+    n_tr = args.learned_train
+    jobs = [(4003, b, min(blk, n_tr - b * blk)) for b in range((n_tr + blk - 1) // blk)]
+    ejobs = [(4002, b, min(blk, args.learned_eval - b * blk))
+             for b in range((args.learned_eval + blk - 1) // blk)]
+    mlp = tpx.Mlp(synth.init_mlp_params(4001), batch=args.learned_batch)
+    lr0, lr1 = 2e-3, 1e-4
+    t0 = time.perf_counter()
+    train_s, seen, loss = 0.0, 0, None
+    for k, cl in enumerate(pool.imap(_cluster_block, jobs)):
+        d = LR.prepare(cl)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        f0, f1 = k / len(jobs), (k + 1) / len(jobs)
+        loss = LR.fit(mlp, d, 1, lr=lr0 * (lr1 / lr0) ** f0, lr_final=lr0 * (lr1 / lr0) ** f1)
+        torch.cuda.synchronize()
+        train_s += time.perf_counter() - t
+        seen += cl["n"]
+        if k % 20 == 0:
+            log(f"learned: block {k}/{len(jobs)}, loss {loss}")
+    wall = time.perf_counter() - t0
+    test = [cl for cl in pool.imap(_cluster_block, ejobs)]
+    ev_parts = [LR.prepare(cl) for cl in test]
+    feat = torch.cat([p[0] for p in ev_parts])
+    hits = torch.cat([p[1] for p in ev_parts])
+    truth = np.concatenate([cl["truth"] for cl in test])
+    mult = np.concatenate([cl["mult"] for cl in test])
+    n_ev = feat.shape[0]
+    refined = LR.predict(mlp, feat, hits)
+    s = LR.score(tpx.hits_to_numpy(hits, n_ev), refined.cpu().numpy(), truth, mult)
+    # inference timing: patches + forward + refine over the held-out clusters
+    cl0 = test[0]
+    ev0 = tpx.to_device_events(cl0["events"])
+    lab0 = torch.from_numpy(np.asarray(cl0["labels"], np.uint32).view(np.int32)).cuda()
+    h0 = ev_parts[0][1]
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    for _ in range(2):
+        tpx.patches(ev0, lab0, h0)
+        LR.predict(mlp, feat, hits)
+    torch.cuda.synchronize()
+    reps = 5
+    e0.record()
+    for _ in range(reps):
+        tpx.patches(ev0, lab0, h0)
+    e1.record()
+    for _ in range(reps):
+        LR.predict(mlp, feat, hits)
+    e2.record()
+    torch.cuda.synchronize()
+    patch_ms = e0.elapsed_time(e1) / reps * (n_ev / cl0["n"])
+    fwd_ms = e1.elapsed_time(e2) / reps
+    flop = 2 * (98 * 256 + 256 * 256 + 256 * 8) * n_ev
+    return dict(
+        workload="clusters with truth: 30% overlapping pairs (separation 0.5-3 px, dt 0-50 ns), "
+                 "sigma U(0.5, 2.5) px, ToT = rint(400 amp), walk 20 ns (1 - amp), jitter 1.5 ns; "
+                 "7x7 ToT/ToA patch, MLP 98-256-256-8, bf16 on MFMA with fp32 accumulation",
+        train_clusters=seen, eval_clusters=int(n_ev), batch=args.learned_batch,
+        final_loss=loss, train_s=train_s, train_wall_s=wall,
+        train_clusters_per_s=seen / max(train_s, 1e-9),
+        inference_clusters_per_s=n_ev / ((patch_ms + fwd_ms) * 1e-3),
+        patch_ms_per_eval_set=patch_ms, forward_refine_ms=fwd_ms,
+        forward_tflops=flop / (fwd_ms * 1e-3) / 1e12, mfma_peak_tflops_bf16=2500.0,
+        plain_path_hits_per_s=plain_hits_per_s, score=s)
+
+
 def run_paper_mode(args, wl):
     """The paper's local-maximum hits (tpx_local_maxima) on the decoded c2
     events: events resident in HBM, HIP-event timing on the call's stream."""
@@ -314,6 +397,12 @@ def main():
                     help="packets per chunk (64 KiB, 1 MiB, 16 MiB)")
     ap.add_argument("--latency-speeds", type=float, nargs="+", default=[1.0, 10.0, 200.0],
                     help="paced replay speedups over acquisition")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--learned-train", type=int, default=10_000_000,
+                    help="training clusters (learned centroider)")
+    ap.add_argument("--learned-eval", type=int, default=1_000_000, help="held-out clusters")
+    ap.add_argument("--learned-block", type=int, default=50_000)
+    ap.add_argument("--learned-batch", type=int, default=4096)
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB before timing "
                          "(calibration of HBM traffic counters)")
@@ -326,6 +415,11 @@ def main():
 
     import synth
 
+    # cluster generators for the learned leg, forked before the GPU is touched
+    pool = None
+    if not args.no_learned:
+        import multiprocessing
+        pool = multiprocessing.get_context("fork").Pool(args.workers)
     t = time.perf_counter()
     wl = synth.make_config("c2", n_shots=args.shots, with_truth=False, workers=args.workers)
     log(f"generated c2: {wl.n_packets} packets in {time.perf_counter() - t:.1f} s")
@@ -387,6 +481,10 @@ def main():
     if not args.no_latency:
         out["stream_latency"] = run_latency(args)
         log(f"latency: {out['stream_latency']}")
+    if pool is not None:
+        out["learned"] = run_learned(args, pool, out["hits_per_s"])
+        pool.terminate()
+        log(f"learned: {out['learned']}")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = run_cpu_baseline(wl, args.cpu_frac)
         log(f"cpu baseline: {out['cpu_baseline']}")

@@ -254,6 +254,62 @@ tpx_status tpx_service_run(tpx_service* sv, int flush, tpx_hit* hits, size_t hit
                            void* stream);
 void tpx_service_destroy(tpx_service* sv);
 
+/* Learned centroider / multiplicity splitter.  A small network reads a 7 x 7
+ * patch around every hit and predicts up to two hits and their multiplicity;
+ * it is trained on clusters with known truth by the gradient and update
+ * calls below.  The ToT-weighted centroid (Sec. V, Centroiding, Eq. 9) places
+ * the patch and stays the fallback.  All arrays are device memory; every call
+ * is ordered on `stream`.
+ *
+ * Patch of a hit: centred on pixel (floor(x + 1/2), floor(y + 1/2)) of its
+ * fp32 centroid; feature c = iy * 7 + ix (ix, iy = pixel - centre + 3 in
+ * 0..6) holds min(summed ToT, 1023) / 1024 and feature 49 + c the pixel's
+ * earliest ToA minus the hit's toa_first, in 64-tick units (0 for an empty
+ * pixel); pixels outside the window are left out.  Features are bfloat16
+ * (round to nearest even).
+ *   tpx_patches  ev, labels, n_ev: events and their labels (tpx_cluster);
+ *                hits, n_hits: their hits in (shot, label) order
+ *                (tpx_centroid); feat: bfloat16 [n_hits][98] out;
+ *                ws: tpx_patch_workspace_bytes(n_hits) bytes.  TPX_EINVAL
+ *                when an event's (shot, label) has no hit.  Synchronises.
+ *
+ * Network: params is fp32 [93192], packed W1[256][98], b1[256], W2[256][256],
+ * b2[256], W3[8][256], b3[8] (W as [out][in]); h1 = relu(W1 f + b1),
+ * h2 = relu(W2 h1 + b2), o = W3 h2 + b3, with bfloat16 features, weights and
+ * hidden activations on the matrix cores and fp32 accumulation and biases.
+ * o[0..2] and o[3..5] are hits A and B as (x - cx, y - cy, (t - toa_first *
+ * 1.5625 ns) / 10 ns), o[6] and o[7] the logits of one and two hits.
+ *   tpx_mlp_forward  out: fp32 [n][8]; ws: tpx_mlp_workspace_bytes(min(n,
+ *                    65536)) bytes.
+ *   tpx_mlp_grad     gradient of the mean loss over a batch of n samples into
+ *                    grad (fp32 [93192]): per sample the squared error of hit
+ *                    A (one hit) or of the cheaper assignment of A and B to
+ *                    the two true hits (two hits), plus the cross entropy of
+ *                    the logits.  truth: fp32 [n][2][3] absolute (x, y in
+ *                    pixels, t in ns; row 1 ignored for one hit); mult:
+ *                    1 or 2 per sample; hits: the samples' hits (patch
+ *                    centre, toa_first).  *loss_h (host, may be NULL: then
+ *                    no synchronisation) = mean loss.  ws:
+ *                    tpx_mlp_workspace_bytes(n) bytes.
+ *   tpx_mlp_adam     one Adam step (step counts from 1) on params with
+ *                    moments m, v (fp32, zero at the start).
+ *   tpx_mlp_refine   refined: fp32 [n][8] = absolute x, y, t_ns of hits A
+ *                    and B, then the probability of two hits, then 0. */
+size_t tpx_patch_workspace_bytes(size_t n_hits);
+tpx_status tpx_patches(tpx_events ev, const uint32_t* labels, size_t n_ev, const tpx_hit* hits,
+                       size_t n_hits, uint16_t* feat, void* ws, size_t ws_bytes, void* stream);
+size_t tpx_mlp_workspace_bytes(size_t batch);
+tpx_status tpx_mlp_forward(const float* params, const uint16_t* feat, size_t n, float* out,
+                           void* ws, size_t ws_bytes, void* stream);
+tpx_status tpx_mlp_grad(const float* params, const uint16_t* feat, const tpx_hit* hits,
+                        const float* truth, const uint8_t* mult, size_t n, float* grad,
+                        float* loss_h, void* ws, size_t ws_bytes, void* stream);
+tpx_status tpx_mlp_adam(float* params, float* m, float* v, const float* grad, size_t n_param,
+                        uint64_t step, float lr, float beta1, float beta2, float eps,
+                        void* stream);
+tpx_status tpx_mlp_refine(const tpx_hit* hits, const float* out, size_t n, float* refined,
+                          void* stream);
+
 const char* tpx_status_str(tpx_status st);
 const char* tpx_last_error(void); /* thread-local detail of the last failure */
 

@@ -69,7 +69,9 @@ EXPORTS = ("tpx_params_default", "tpx_unwrap_state_init", "tpx_workspace_bytes",
            "tpx_stream_get_state", "tpx_stream_set_state", "tpx_stream_destroy",
            "tpx_status_str", "tpx_last_error", "tpx_stream_fallback_count",
            "tpx_stream_set_timing", "tpx_stream_get_timing", "tpx_stream_stage_name",
-           "tpx_service_create", "tpx_service_submit", "tpx_service_run", "tpx_service_destroy")
+           "tpx_service_create", "tpx_service_submit", "tpx_service_run", "tpx_service_destroy",
+           "tpx_patch_workspace_bytes", "tpx_patches", "tpx_mlp_workspace_bytes",
+           "tpx_mlp_forward", "tpx_mlp_grad", "tpx_mlp_adam", "tpx_mlp_refine")
 
 _lib = None
 
@@ -104,6 +106,18 @@ def load(path=LIB_PATH):
     lib.tpx_stream_set_state.argtypes = [P, P, S]
     lib.tpx_stream_destroy.argtypes = [P]
     lib.tpx_stream_destroy.restype = None
+    lib.tpx_patch_workspace_bytes.argtypes = [S]
+    lib.tpx_patch_workspace_bytes.restype = S
+    lib.tpx_patches.argtypes = [Events, P, S, P, S, P, P, S, P]
+    lib.tpx_mlp_workspace_bytes.argtypes = [S]
+    lib.tpx_mlp_workspace_bytes.restype = S
+    lib.tpx_mlp_forward.argtypes = [P, P, S, P, P, S, P]
+    lib.tpx_mlp_grad.argtypes = [P, P, P, P, P, S, P, P, P, S, P]
+    lib.tpx_mlp_adam.argtypes = [P, P, P, P, S, ctypes.c_uint64, ctypes.c_float, ctypes.c_float,
+                                 ctypes.c_float, ctypes.c_float, P]
+    lib.tpx_mlp_refine.argtypes = [P, P, S, P, P]
+    for f in ("tpx_patches", "tpx_mlp_forward", "tpx_mlp_grad", "tpx_mlp_adam", "tpx_mlp_refine"):
+        getattr(lib, f).restype = I
     lib.tpx_status_str.argtypes = [I]
     lib.tpx_status_str.restype = ctypes.c_char_p
     lib.tpx_last_error.argtypes = []
@@ -433,3 +447,104 @@ def process_stream(packets, flush=True, **kw):
         return s.process(packets, flush=flush)
     finally:
         s.close()
+
+
+# ------------------------------------------------------- learned centroider
+MLP_IN, MLP_HID, MLP_OUT, MLP_NPARAM = 98, 256, 8, 93192
+
+
+def centroid_dev(ev, labels, trig, params=None, ws=None):
+    """tpx_centroid into device memory: uint8 tensor [n_hits, 48]."""
+    torch = _torch()
+    lib = load()
+    n = ev["x"].numel()
+    p = params or make_params()
+    trig = _u64(torch, trig)
+    hits = torch.empty((max(n, 1), 48), dtype=torch.uint8, device="cuda")
+    ws = workspace(0, n) if ws is None else ws
+    nh = ctypes.c_size_t()
+    rc = lib.tpx_centroid(events_struct(ev), _ptr(labels), n, _ptr(trig), trig.numel(),
+                          ctypes.byref(p), _ptr(hits), n, ctypes.byref(nh), _ptr(ws),
+                          ws.numel(), _stream(torch))
+    _check(rc, "tpx_centroid")
+    return hits[:nh.value]
+
+
+def patches(ev, labels, hits):
+    """tpx_patches: bfloat16 bit patterns as an int16 tensor [n_hits, 98]."""
+    torch = _torch()
+    lib = load()
+    n_h = hits.shape[0]
+    feat = torch.empty((max(n_h, 1), MLP_IN), dtype=torch.int16, device="cuda")
+    ws = torch.empty(lib.tpx_patch_workspace_bytes(n_h), dtype=torch.uint8, device="cuda")
+    rc = lib.tpx_patches(events_struct(ev), _ptr(labels), ev["x"].numel(), _ptr(hits), n_h,
+                         _ptr(feat), _ptr(ws), ws.numel(), _stream(torch))
+    _check(rc, "tpx_patches")
+    return feat[:n_h]
+
+
+def refine(hits, out):
+    """tpx_mlp_refine: fp32 tensor [n, 8] (x, y, t_ns of hits A and B,
+    probability of two hits, 0)."""
+    torch = _torch()
+    n = out.shape[0]
+    r = torch.empty((max(n, 1), 8), dtype=torch.float32, device="cuda")
+    _check(load().tpx_mlp_refine(_ptr(hits), _ptr(out), n, _ptr(r), _stream(torch)),
+           "tpx_mlp_refine")
+    return r[:n]
+
+
+class Mlp:
+    """Parameters, Adam moments and workspaces of the 98-256-256-8 network;
+    every call runs the library's kernels."""
+
+    def __init__(self, params, batch=4096):
+        torch = _torch()
+        self.torch = torch
+        self.lib = load()
+        p = params if isinstance(params, torch.Tensor) else torch.from_numpy(
+            np.ascontiguousarray(params, np.float32))
+        assert p.numel() == MLP_NPARAM
+        self.p = p.to(device="cuda", dtype=torch.float32).contiguous().clone()
+        self.m = torch.zeros_like(self.p)
+        self.v = torch.zeros_like(self.p)
+        self.g = torch.zeros_like(self.p)
+        self.step = 0
+        self.batch = batch
+        self.ws = torch.empty(self.lib.tpx_mlp_workspace_bytes(batch), dtype=torch.uint8,
+                              device="cuda")
+        self.fws = None
+
+    def forward(self, feat):
+        torch = self.torch
+        n = feat.shape[0]
+        out = torch.empty((max(n, 1), MLP_OUT), dtype=torch.float32, device="cuda")
+        need = self.lib.tpx_mlp_workspace_bytes(min(n, 65536))
+        if self.fws is None or self.fws.numel() < need:
+            self.fws = torch.empty(need, dtype=torch.uint8, device="cuda")
+        _check(self.lib.tpx_mlp_forward(_ptr(self.p), _ptr(feat), n, _ptr(out), _ptr(self.fws),
+                                        self.fws.numel(), _stream(torch)), "tpx_mlp_forward")
+        return out[:n]
+
+    def grad(self, feat, hits, truth, mult, want_loss=True):
+        """Gradient of the mean loss into self.g; returns the loss (or None)."""
+        n = feat.shape[0]
+        assert n <= self.batch
+        loss = ctypes.c_float()
+        rc = self.lib.tpx_mlp_grad(_ptr(self.p), _ptr(feat), _ptr(hits), _ptr(truth), _ptr(mult),
+                                   n, _ptr(self.g), ctypes.byref(loss) if want_loss else None,
+                                   _ptr(self.ws), self.ws.numel(), _stream(self.torch))
+        _check(rc, "tpx_mlp_grad")
+        return float(loss.value) if want_loss else None
+
+    def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        self.step += 1
+        _check(self.lib.tpx_mlp_adam(_ptr(self.p), _ptr(self.m), _ptr(self.v), _ptr(self.g),
+                                     MLP_NPARAM, self.step, lr, beta1, beta2, eps,
+                                     _stream(self.torch)), "tpx_mlp_adam")
+
+    def train_step(self, feat, hits, truth, mult, lr, want_loss=False):
+        loss = self.grad(feat, hits, truth, mult, want_loss)
+        self.adam(lr)
+        return loss
+

@@ -1,0 +1,462 @@
+// Learned centroider / multiplicity splitter: 7 x 7 ToT/ToA patches of the
+// clusters, and a 98 -> 256 -> 256 -> 8 MLP trained and run by the kernels
+// below (bfloat16 operands on the matrix cores, fp32 accumulation).
+//
+// The patch of a hit is centred on the pixel nearest to its ToT-weighted
+// centroid (Sec. V, Centroiding, Eq. 9); plane 0 holds the summed ToT of each
+// pixel / 1024, plane 1 its earliest ToA minus the hit's earliest ToA in
+// 64-tick (100 ns) units.  Outputs: two hits (x - cx, y - cy, (t - ToA_first)
+// / 10 ns) and the logits of one and two hits.
+//
+// Layout.  Parameters are one fp32 array packed W1[256][98], b1[256],
+// W2[256][256], b2[256], W3[8][256], b3[8] (W as [out][in]).  Features are
+// bfloat16 [n][98].  Every layer is one GEMM C = A * B with A(m, k) =
+// A[m * sam + k * sak] and B(k, n) = B[k * sbk + n * sbn], so the transposed
+// products of the backward pass need no transposed copies; the epilogue adds
+// the bias, applies ReLU or the ReLU mask of the stored activation, and
+// writes fp32 and/or bfloat16.
+#include "tpx_kernels.h"
+
+namespace tpx {
+namespace {
+
+constexpr int kIn = 98, kHid = 256, kOut = 8, kCells = 49, kHalf = 3, kSide = 7;
+constexpr size_t kOffW1 = 0, kOffB1 = kOffW1 + (size_t)kHid * kIn, kOffW2 = kOffB1 + kHid,
+                 kOffB2 = kOffW2 + (size_t)kHid * kHid, kOffW3 = kOffB2 + kHid,
+                 kOffB3 = kOffW3 + (size_t)kOut * kHid, kNParam = kOffB3 + kOut;
+static_assert(kNParam == 93192, "parameter count of the 98-256-256-8 network");
+constexpr size_t kFwdChunk = 65536;  // rows per forward pass in tpx_mlp_forward
+
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// fp32 -> bfloat16, round to nearest, ties to even (finite inputs)
+__device__ __forceinline__ uint16_t to_bf16(float f) {
+    const uint32_t u = __float_as_uint(f);
+    return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float from_bf16(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+// patch centre: x + 1/2 rounded down, in fp32
+__device__ __forceinline__ int centre_of(float v) { return (int)floorf(v + 0.5f); }
+
+// ------------------------------------------------------------------ patches
+__global__ void k_patch_clear(uint32_t* acc, uint64_t n_hits) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_hits * kIn) return;
+    acc[i] = (i % kIn) < kCells ? 0u : 0xFFFFFFFFu;
+}
+
+// one thread per event: find its hit by (shot, label) in the (shot, label)
+// ordered hit list, then add its ToT and fold its ToA into the pixel's cell
+__global__ void k_patch_accum(tpx_events ev, const uint32_t* labels, uint64_t n_ev,
+                              const tpx_hit* hits, uint64_t n_hits, uint32_t* acc, int* err) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_ev) return;
+    const uint64_t key = ((uint64_t)ev.shot[i] << 32) | labels[i];
+    uint64_t lo = 0, hi = n_hits;
+    while (lo < hi) {
+        const uint64_t mid = (lo + hi) >> 1;
+        const uint64_t k = (hits[mid].shot << 32) | hits[mid].label;
+        if (k < key) lo = mid + 1;
+        else hi = mid;
+    }
+    if (lo >= n_hits || ((hits[lo].shot << 32) | hits[lo].label) != key) {
+        atomicOr(err, 1);
+        return;
+    }
+    const tpx_hit& h = hits[lo];
+    const int ix = (int)ev.x[i] - centre_of(h.x) + kHalf;
+    const int iy = (int)ev.y[i] - centre_of(h.y) + kHalf;
+    if (ix < 0 || ix >= kSide || iy < 0 || iy >= kSide) return;
+    const int c = iy * kSide + ix;
+    const uint64_t toa = ev.toa[i];
+    const uint64_t d = toa > h.toa_first ? toa - h.toa_first : 0;
+    atomicAdd(&acc[lo * kIn + c], (uint32_t)ev.tot[i]);
+    atomicMin(&acc[lo * kIn + kCells + c], d < 0xFFFFFFFEull ? (uint32_t)d : 0xFFFFFFFEu);
+}
+
+__global__ void k_patch_finish(const uint32_t* acc, uint64_t n_hits, uint16_t* feat) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_hits * kCells) return;
+    const uint64_t h = i / kCells, c = i % kCells;
+    const uint32_t s = acc[h * kIn + c];
+    const uint32_t d = acc[h * kIn + kCells + c];
+    feat[h * kIn + c] = to_bf16((float)(s < 1023u ? s : 1023u) * (1.0f / 1024.0f));
+    feat[h * kIn + kCells + c] = d == 0xFFFFFFFFu ? (uint16_t)0 : to_bf16((float)d * (1.0f / 64.0f));
+}
+
+// --------------------------------------------------------------------- GEMM
+struct Gemm {
+    const uint16_t* A;
+    int64_t sam, sak;
+    const uint16_t* B;
+    int64_t sbk, sbn;
+    int M, N, K;
+    const float* bias;      // [N] or null
+    int relu;
+    const uint16_t* mask;   // keep (m, n) only where mask[m * ldmask + n] > 0, or null
+    int64_t ldmask;
+    float* C32;             // or null
+    int64_t ldc32;
+    uint16_t* C16;          // or null
+    int64_t ldc16;
+};
+
+constexpr int kTM = 64, kTN = 64, kTK = 32, kPitch = kTK + 8;
+
+// 256 threads = 4 waves in 2 x 2; each wave owns a 32 x 32 block of the
+// 64 x 64 tile as 2 x 2 MFMA 16x16x16 blocks.  Operand layout of the MFMA:
+// lane l holds A[l % 16][4 (l / 16) .. +3] and B[4 (l / 16) .. +3][l % 16];
+// result lane l holds C[4 (l / 16) + r][l % 16], r = 0..3.
+__global__ __launch_bounds__(256) void k_gemm(Gemm g) {
+    __shared__ __align__(16) uint16_t As[kTM][kPitch];
+    __shared__ __align__(16) uint16_t Bs[kTN][kPitch];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wm = w >> 1, wn = w & 1;
+    const int m0 = blockIdx.y * kTM, n0 = blockIdx.x * kTN;
+    const bool a_k = g.sak == 1, b_k = g.sbk == 1;
+    f32x4 acc[2][2];
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < g.K; k0 += kTK) {
+#pragma unroll
+        for (int r = 0; r < (kTM * kTK) / 256; ++r) {
+            const int e = tid + 256 * r;
+            const int m = a_k ? e >> 5 : e & 63;
+            const int k = a_k ? e & 31 : e >> 6;
+            const int gm = m0 + m, gk = k0 + k;
+            As[m][k] = (gm < g.M && gk < g.K) ? g.A[gm * g.sam + gk * g.sak] : (uint16_t)0;
+            const int n = b_k ? e >> 5 : e & 63;
+            const int kb = b_k ? e & 31 : e >> 6;
+            const int gn = n0 + n, gkb = k0 + kb;
+            Bs[n][kb] = (gn < g.N && gkb < g.K) ? g.B[gkb * g.sbk + gn * g.sbn] : (uint16_t)0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < kTK; kk += 16) {
+            s16x4 a[2], b[2];
+            const int kq = kk + 4 * (lane >> 4);
+            for (int mb = 0; mb < 2; ++mb)
+                a[mb] = *(const s16x4*)&As[wm * 32 + mb * 16 + (lane & 15)][kq];
+            for (int nb = 0; nb < 2; ++nb)
+                b[nb] = *(const s16x4*)&Bs[wn * 32 + nb * 16 + (lane & 15)][kq];
+            for (int mb = 0; mb < 2; ++mb)
+                for (int nb = 0; nb < 2; ++nb)
+                    acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[mb], b[nb],
+                                                                            acc[mb][nb], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    for (int mb = 0; mb < 2; ++mb)
+        for (int nb = 0; nb < 2; ++nb)
+            for (int r = 0; r < 4; ++r) {
+                const int m = m0 + wm * 32 + mb * 16 + 4 * (lane >> 4) + r;
+                const int n = n0 + wn * 32 + nb * 16 + (lane & 15);
+                if (m >= g.M || n >= g.N) continue;
+                float v = acc[mb][nb][r];
+                if (g.bias) v += g.bias[n];
+                if (g.relu) v = v > 0.f ? v : 0.f;
+                if (g.mask && !(from_bf16(g.mask[m * g.ldmask + n]) > 0.f)) v = 0.f;
+                if (g.C32) g.C32[m * g.ldc32 + n] = v;
+                if (g.C16) g.C16[m * g.ldc16 + n] = to_bf16(v);
+            }
+}
+
+void gemm(const Gemm& g, hipStream_t s) {
+    if (g.M <= 0 || g.N <= 0) return;
+    dim3 grid((g.N + kTN - 1) / kTN, (g.M + kTM - 1) / kTM);
+    hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, s, g);
+}
+
+// ------------------------------------------------------- loss, sums, update
+__global__ void k_cast_bf16(const float* p, uint64_t n, uint16_t* q) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) q[i] = to_bf16(p[i]);
+}
+
+__global__ void k_zero_f32(float* p, int n) {
+    if ((int)threadIdx.x < n) p[threadIdx.x] = 0.f;
+}
+
+// one thread per sample: targets relative to the patch centre and earliest
+// ToA, the loss (pair matched the cheaper way round, ties A-first), dL/dO / n
+__global__ void k_loss(const float* O, const tpx_hit* hits, const float* truth,
+                       const uint8_t* mult, int n, float* G32, uint16_t* G16, float* loss_sum) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    float li = 0.f;
+    if (i < n) {
+        const tpx_hit& h = hits[i];
+        const float cx = (float)centre_of(h.x), cy = (float)centre_of(h.y);
+        const double t0 = (double)h.toa_first * 1.5625;
+        float T[2][3];
+        for (int k = 0; k < 2; ++k) {
+            T[k][0] = truth[i * 6 + 3 * k + 0] - cx;
+            T[k][1] = truth[i * 6 + 3 * k + 1] - cy;
+            T[k][2] = (float)(((double)truth[i * 6 + 3 * k + 2] - t0) / 10.0);
+        }
+        float o[8];
+        for (int k = 0; k < 8; ++k) o[k] = O[i * 8 + k];
+        const bool two = mult[i] == 2;
+        float ea = 0.f, c1b = 0.f, c2 = 0.f;
+        for (int k = 0; k < 3; ++k) {
+            ea += (o[k] - T[0][k]) * (o[k] - T[0][k]);
+            c1b += (o[3 + k] - T[1][k]) * (o[3 + k] - T[1][k]);
+            c2 += (o[k] - T[1][k]) * (o[k] - T[1][k]) + (o[3 + k] - T[0][k]) * (o[3 + k] - T[0][k]);
+        }
+        const float c1 = ea + c1b;
+        const bool swap = two && c2 < c1;
+        const float lpos = two ? fminf(c1, c2) : ea;
+        const float mx = fmaxf(o[6], o[7]);
+        const float lse = mx + logf(expf(o[6] - mx) + expf(o[7] - mx));
+        li = lpos + lse - (two ? o[7] : o[6]);
+        const float inv = 1.0f / (float)n;
+        float g[8];
+        for (int k = 0; k < 3; ++k) {
+            g[k] = 2.f * (o[k] - (swap ? T[1][k] : T[0][k])) * inv;
+            g[3 + k] = two ? 2.f * (o[3 + k] - (swap ? T[0][k] : T[1][k])) * inv : 0.f;
+        }
+        const float p1 = expf(o[6] - lse), p2 = expf(o[7] - lse);
+        g[6] = (p1 - (two ? 0.f : 1.f)) * inv;
+        g[7] = (p2 - (two ? 1.f : 0.f)) * inv;
+        for (int k = 0; k < 8; ++k) {
+            G32[i * 8 + k] = g[k];
+            G16[i * 8 + k] = to_bf16(g[k]);
+        }
+    }
+    // block sum of the sample losses, one atomic per block
+    __shared__ float part[4];
+    float v = li;
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(loss_sum, part[0] + part[1] + part[2] + part[3]);
+}
+
+// column sums of an fp32 [rows][cols] matrix: one workgroup per column
+__global__ void k_colsum(const float* a, int rows, int cols, float* out) {
+    const int c = blockIdx.x;
+    float v = 0.f;
+    for (int r = threadIdx.x; r < rows; r += blockDim.x) v += a[(int64_t)r * cols + c];
+    __shared__ float part[4];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) out[c] = part[0] + part[1] + part[2] + part[3];
+}
+
+__global__ void k_adam(float* p, float* m, float* v, const float* g, uint64_t n, float lr,
+                       float b1, float b2, float eps, float c1, float c2) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+__global__ void k_refine(const tpx_hit* hits, const float* O, uint64_t n, float* out) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const tpx_hit& h = hits[i];
+    const float cx = (float)centre_of(h.x), cy = (float)centre_of(h.y);
+    const double t0 = (double)h.toa_first * 1.5625;
+    for (int k = 0; k < 2; ++k) {
+        out[i * 8 + 3 * k + 0] = cx + O[i * 8 + 3 * k + 0];
+        out[i * 8 + 3 * k + 1] = cy + O[i * 8 + 3 * k + 1];
+        out[i * 8 + 3 * k + 2] = (float)(t0 + 10.0 * (double)O[i * 8 + 3 * k + 2]);
+    }
+    out[i * 8 + 6] = 1.f / (1.f + expf(O[i * 8 + 6] - O[i * 8 + 7]));
+    out[i * 8 + 7] = 0.f;
+}
+
+inline unsigned blocks(uint64_t n, unsigned t) { return (unsigned)((n + t - 1) / t); }
+
+// workspace of one pass over `rows` samples
+struct MlpWs {
+    uint16_t *wq, *h1, *h2, *g16, *z2_16, *z1_16;
+    float *o, *g32, *z2_32, *z1_32, *loss;
+};
+
+size_t mlp_ws_bytes(size_t rows) {
+    auto r = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    return r(kNParam * 2) + 2 * r(rows * kHid * 2) + r(rows * kOut * 2) + 2 * r(rows * kHid * 2) +
+           r(rows * kOut * 4) + r(rows * kOut * 4) + 2 * r(rows * kHid * 4) + r(64);
+}
+
+MlpWs carve_mlp(void* ws, size_t rows) {
+    uintptr_t p = (uintptr_t)ws;
+    auto take = [&](size_t b) {
+        const uintptr_t q = p;
+        p += (b + 255) & ~(size_t)255;
+        return (void*)q;
+    };
+    MlpWs w;
+    w.wq = (uint16_t*)take(kNParam * 2);
+    w.h1 = (uint16_t*)take(rows * kHid * 2);
+    w.h2 = (uint16_t*)take(rows * kHid * 2);
+    w.g16 = (uint16_t*)take(rows * kOut * 2);
+    w.z2_16 = (uint16_t*)take(rows * kHid * 2);
+    w.z1_16 = (uint16_t*)take(rows * kHid * 2);
+    w.o = (float*)take(rows * kOut * 4);
+    w.g32 = (float*)take(rows * kOut * 4);
+    w.z2_32 = (float*)take(rows * kHid * 4);
+    w.z1_32 = (float*)take(rows * kHid * 4);
+    w.loss = (float*)take(64);
+    return w;
+}
+
+Gemm mk(const uint16_t* A, int64_t sam, int64_t sak, const uint16_t* B, int64_t sbk, int64_t sbn,
+        int M, int N, int K) {
+    Gemm g{};
+    g.A = A, g.sam = sam, g.sak = sak, g.B = B, g.sbk = sbk, g.sbn = sbn;
+    g.M = M, g.N = N, g.K = K;
+    return g;
+}
+
+// forward of `rows` samples from feat into o (fp32 [rows][8]); wq holds the
+// bfloat16 weights; h1, h2 keep the bfloat16 activations for the backward
+void forward(const float* params, const uint16_t* wq, const uint16_t* feat, int rows, uint16_t* h1,
+             uint16_t* h2, float* o, hipStream_t s) {
+    Gemm g = mk(feat, kIn, 1, wq + kOffW1, 1, kIn, rows, kHid, kIn);
+    g.bias = params + kOffB1, g.relu = 1, g.C16 = h1, g.ldc16 = kHid;
+    gemm(g, s);
+    g = mk(h1, kHid, 1, wq + kOffW2, 1, kHid, rows, kHid, kHid);
+    g.bias = params + kOffB2, g.relu = 1, g.C16 = h2, g.ldc16 = kHid;
+    gemm(g, s);
+    g = mk(h2, kHid, 1, wq + kOffW3, 1, kHid, rows, kOut, kHid);
+    g.bias = params + kOffB3, g.C32 = o, g.ldc32 = kOut;
+    gemm(g, s);
+}
+
+}  // namespace
+}  // namespace tpx
+
+using namespace tpx;
+
+extern "C" {
+
+size_t tpx_patch_workspace_bytes(size_t n_hits) { return n_hits * kIn * 4 + 256; }
+
+tpx_status tpx_patches(tpx_events ev, const uint32_t* labels, size_t n_ev, const tpx_hit* hits,
+                       size_t n_hits, uint16_t* feat, void* ws, size_t ws_bytes, void* stream) {
+    if (n_ev && (!ev.x || !ev.y || !ev.tot || !ev.shot || !ev.toa || !labels))
+        return report(TPX_EINVAL, "an event array is NULL");
+    if (n_hits && (!hits || !feat)) return report(TPX_EINVAL, "hits or feat is NULL");
+    if (n_ev && !n_hits) return report(TPX_EINVAL, "events without hits");
+    if (!ws || ws_bytes < tpx_patch_workspace_bytes(n_hits))
+        return report(TPX_EINVAL, "workspace too small");
+    if (n_hits == 0) return TPX_OK;
+    hipStream_t s = (hipStream_t)stream;
+    uint32_t* acc = (uint32_t*)ws;
+    int* err = (int*)((char*)ws + n_hits * kIn * 4);
+    hipLaunchKernelGGL(k_patch_clear, dim3(blocks(n_hits * kIn, 256)), dim3(256), 0, s, acc,
+                       (uint64_t)n_hits);
+    hipLaunchKernelGGL(k_zero_f32, dim3(1), dim3(64), 0, s, (float*)err, 1);
+    if (n_ev)
+        hipLaunchKernelGGL(k_patch_accum, dim3(blocks(n_ev, 256)), dim3(256), 0, s, ev, labels,
+                           (uint64_t)n_ev, hits, (uint64_t)n_hits, acc, err);
+    hipLaunchKernelGGL(k_patch_finish, dim3(blocks(n_hits * kCells, 256)), dim3(256), 0, s, acc,
+                       (uint64_t)n_hits, feat);
+    int e = 0;
+    if (hipMemcpyAsync(&e, err, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return report(TPX_EHIP, "patch kernels failed");
+    if (e) return report(TPX_EINVAL, "an event's (shot, label) has no hit");
+    return TPX_OK;
+}
+
+size_t tpx_mlp_workspace_bytes(size_t batch) { return mlp_ws_bytes(batch); }
+
+tpx_status tpx_mlp_forward(const float* params, const uint16_t* feat, size_t n, float* out,
+                           void* ws, size_t ws_bytes, void* stream) {
+    if (n && (!params || !feat || !out)) return report(TPX_EINVAL, "NULL argument");
+    const size_t rows = n < kFwdChunk ? n : kFwdChunk;
+    if (!ws || ws_bytes < mlp_ws_bytes(rows)) return report(TPX_EINVAL, "workspace too small");
+    if (n == 0) return TPX_OK;
+    hipStream_t s = (hipStream_t)stream;
+    MlpWs w = carve_mlp(ws, rows);
+    hipLaunchKernelGGL(k_cast_bf16, dim3(blocks(kNParam, 256)), dim3(256), 0, s, params,
+                       (uint64_t)kNParam, w.wq);
+    for (size_t r0 = 0; r0 < n; r0 += rows) {
+        const int m = (int)(n - r0 < rows ? n - r0 : rows);
+        forward(params, w.wq, feat + r0 * kIn, m, w.h1, w.h2, out + r0 * kOut, s);
+    }
+    if (hipGetLastError() != hipSuccess) return report(TPX_EHIP, "forward launch failed");
+    return TPX_OK;
+}
+
+tpx_status tpx_mlp_grad(const float* params, const uint16_t* feat, const tpx_hit* hits,
+                        const float* truth, const uint8_t* mult, size_t n, float* grad,
+                        float* loss_h, void* ws, size_t ws_bytes, void* stream) {
+    if (!params || !grad || (n && (!feat || !hits || !truth || !mult)))
+        return report(TPX_EINVAL, "NULL argument");
+    if (n == 0 || n > (1u << 24)) return report(TPX_EINVAL, "batch size out of range");
+    if (!ws || ws_bytes < mlp_ws_bytes(n)) return report(TPX_EINVAL, "workspace too small");
+    hipStream_t s = (hipStream_t)stream;
+    const int B = (int)n;
+    MlpWs w = carve_mlp(ws, n);
+    hipLaunchKernelGGL(k_cast_bf16, dim3(blocks(kNParam, 256)), dim3(256), 0, s, params,
+                       (uint64_t)kNParam, w.wq);
+    forward(params, w.wq, feat, B, w.h1, w.h2, w.o, s);
+    hipLaunchKernelGGL(k_zero_f32, dim3(1), dim3(64), 0, s, w.loss, 1);
+    hipLaunchKernelGGL(k_loss, dim3(blocks(n, 256)), dim3(256), 0, s, w.o, hits, truth, mult, B,
+                       w.g32, w.g16, w.loss);
+    // layer 3: dW3 = G^T H2, db3 = sum G, dZ2 = (G W3) * [H2 > 0]
+    Gemm g = mk(w.g16, 1, kOut, w.h2, kHid, 1, kOut, kHid, B);
+    g.C32 = grad + kOffW3, g.ldc32 = kHid;
+    gemm(g, s);
+    hipLaunchKernelGGL(k_colsum, dim3(kOut), dim3(256), 0, s, w.g32, B, kOut, grad + kOffB3);
+    g = mk(w.g16, kOut, 1, w.wq + kOffW3, kHid, 1, B, kHid, kOut);
+    g.mask = w.h2, g.ldmask = kHid, g.C32 = w.z2_32, g.ldc32 = kHid, g.C16 = w.z2_16, g.ldc16 = kHid;
+    gemm(g, s);
+    // layer 2: dW2 = dZ2^T H1, db2 = sum dZ2, dZ1 = (dZ2 W2) * [H1 > 0]
+    g = mk(w.z2_16, 1, kHid, w.h1, kHid, 1, kHid, kHid, B);
+    g.C32 = grad + kOffW2, g.ldc32 = kHid;
+    gemm(g, s);
+    hipLaunchKernelGGL(k_colsum, dim3(kHid), dim3(256), 0, s, w.z2_32, B, kHid, grad + kOffB2);
+    g = mk(w.z2_16, kHid, 1, w.wq + kOffW2, kHid, 1, B, kHid, kHid);
+    g.mask = w.h1, g.ldmask = kHid, g.C32 = w.z1_32, g.ldc32 = kHid, g.C16 = w.z1_16, g.ldc16 = kHid;
+    gemm(g, s);
+    // layer 1: dW1 = dZ1^T X, db1 = sum dZ1
+    g = mk(w.z1_16, 1, kHid, feat, kIn, 1, kHid, kIn, B);
+    g.C32 = grad + kOffW1, g.ldc32 = kIn;
+    gemm(g, s);
+    hipLaunchKernelGGL(k_colsum, dim3(kHid), dim3(256), 0, s, w.z1_32, B, kHid, grad + kOffB1);
+    if (hipGetLastError() != hipSuccess) return report(TPX_EHIP, "gradient launch failed");
+    if (loss_h) {
+        float l = 0.f;
+        if (hipMemcpyAsync(&l, w.loss, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return report(TPX_EHIP, "loss copy failed");
+        *loss_h = l / (float)n;
+    }
+    return TPX_OK;
+}
+
+tpx_status tpx_mlp_adam(float* params, float* m, float* v, const float* grad, size_t n_param,
+                        uint64_t step, float lr, float beta1, float beta2, float eps,
+                        void* stream) {
+    if (!params || !m || !v || !grad) return report(TPX_EINVAL, "NULL argument");
+    if (step == 0) return report(TPX_EINVAL, "step counts from 1");
+    const float c1 = (float)(1.0 - pow((double)beta1, (double)step));
+    const float c2 = (float)(1.0 - pow((double)beta2, (double)step));
+    hipLaunchKernelGGL(k_adam, dim3(blocks(n_param, 256)), dim3(256), 0, (hipStream_t)stream,
+                       params, m, v, grad, (uint64_t)n_param, lr, beta1, beta2, eps, c1, c2);
+    if (hipGetLastError() != hipSuccess) return report(TPX_EHIP, "adam launch failed");
+    return TPX_OK;
+}
+
+tpx_status tpx_mlp_refine(const tpx_hit* hits, const float* out, size_t n, float* refined,
+                          void* stream) {
+    if (n && (!hits || !out || !refined)) return report(TPX_EINVAL, "NULL argument");
+    if (n == 0) return TPX_OK;
+    hipLaunchKernelGGL(k_refine, dim3(blocks(n, 256)), dim3(256), 0, (hipStream_t)stream, hits,
+                       out, (uint64_t)n, refined);
+    if (hipGetLastError() != hipSuccess) return report(TPX_EHIP, "refine launch failed");
+    return TPX_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,221 @@
+"""The learned centroider on the GPU through the C ABI, against the oracle
+(oracle/learned.py): patches bit-exact; forward outputs, gradients, the Adam
+step and the refined hits within tolerances derived from bfloat16 rounding;
+and training on generated clusters must beat the weighted centroid where it
+cannot be right (overlapping pairs, walk-biased times)."""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import learned as L
+
+pytestmark = pytest.mark.gpu
+
+# bfloat16 keeps 8 significant bits: each rounding is within 2^-9 relative.
+# Features and weights are rounded on both sides; the kernels also round the
+# two hidden activations and the three backward operands (dL/dO, dZ2, dZ1).
+# Independent roundings over sums of 98-256 terms add up like a random walk,
+# so outputs and gradients stay within a few 2^-9 of the float64 result,
+# relative to their RMS; 2e-2 leaves a margin of about 4.
+REL_TOL = 2e-2
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def tpx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2603_04942_amd as t
+    t.load()
+    return t
+
+
+def _rand_params(seed):
+    rng = np.random.default_rng(seed)
+    p = synth.init_mlp_params(seed).astype(np.float64)
+    d = L.unpack(p)
+    for b in ("b1", "b2", "b3"):
+        d[b][:] = rng.normal(0, 0.2, d[b].shape)
+    return L.pack(d).astype(np.float32)
+
+
+def _oracle_inputs(orc, cl):
+    e = cl["events"]
+    hits = orc.centroid(e["x"], e["y"], e["tot"], e["shot"], e["toa"], cl["labels"],
+                        np.zeros(cl["n"], np.uint64))
+    feat = L.patches(e["x"], e["y"], e["tot"], e["toa"], e["shot"], cl["labels"], hits)
+    return hits, feat
+
+
+@pytest.mark.parametrize("n", [1, 37, 700])
+def test_patches_bit_exact_generated(tpx, orc, n):
+    cl = synth.make_clusters(100 + n, n)
+    hits, ref = _oracle_inputs(orc, cl)
+    from paper_2603_04942_amd.learned import prepare
+    feat, _, _, _ = prepare(cl)
+    got = feat.cpu().numpy().view(np.uint16)
+    assert got.shape == ref.shape
+    bad = np.argwhere(got != ref)
+    assert bad.size == 0, f"{len(bad)} features differ, first {bad[:5]}"
+
+
+def test_patches_bit_exact_clustered_stream(tpx, orc):
+    """Patches of every hit of a decoded and clustered c1 workload (many
+    clusters per shot, noise, pairs)."""
+    import torch
+    w = synth.make_config("c1", n_shots=150)
+    d = orc.decode(w.packets, pix_epoch0=w.pix_epoch0, tdc_epoch0=w.tdc_epoch0)
+    e = d["events"]
+    lab, _ = orc.cluster(e["x"], e["y"], e["shot"], e["toa"])
+    hits = orc.centroid(e["x"], e["y"], e["tot"], e["shot"], e["toa"], lab, d["trig"])
+    ref = L.patches(e["x"], e["y"], e["tot"], e["toa"], e["shot"], lab, hits)
+    ev = tpx.to_device_events(e)
+    glab, _ = tpx.cluster(ev)
+    assert np.array_equal(glab.cpu().numpy().view(np.uint32), lab.astype(np.uint32))
+    gh = tpx.centroid_dev(ev, glab, d["trig"])
+    got = tpx.patches(ev, glab, gh).cpu().numpy().view(np.uint16)
+    _say(f"c1 patches: {len(hits)} hits")
+    assert np.array_equal(got, ref)
+
+
+def test_patches_missing_hit_is_an_error(tpx):
+    import torch
+    cl = synth.make_clusters(7, 5)
+    from paper_2603_04942_amd.learned import prepare
+    _, hits, _, _ = prepare(cl)
+    ev = tpx.to_device_events(cl["events"])
+    labels = torch.from_numpy(cl["labels"].view(np.int32)).cuda()
+    with pytest.raises(tpx.TpxError) as e:
+        tpx.patches(ev, labels, hits[:4])        # sample 4 has no hit
+    assert e.value.rc == tpx.EINVAL
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+
+
+@pytest.mark.parametrize("n", [1, 65, 300])
+def test_forward_matches_oracle(tpx, n):
+    import torch
+    rng = np.random.default_rng(n)
+    feat = L.bf16_bits(rng.uniform(0, 1, (n, L.IN)).astype(np.float32))
+    p = _rand_params(n)
+    ref, _ = L.forward(p, feat)
+    mlp = tpx.Mlp(p, batch=max(n, 1))
+    out = mlp.forward(torch.from_numpy(feat.view(np.int16)).cuda()).cpu().numpy()
+    rms = float(np.sqrt(np.mean(ref ** 2)))
+    assert np.abs(out - ref).max() <= REL_TOL * rms, (np.abs(out - ref).max(), rms)
+
+
+def test_forward_large_batch_chunks(tpx):
+    """More rows than one forward pass holds (65,536): chunked passes agree
+    with the oracle on sampled rows."""
+    import torch
+    n = 70_001
+    rng = np.random.default_rng(5)
+    feat = L.bf16_bits(rng.uniform(0, 1, (n, L.IN)).astype(np.float32))
+    p = _rand_params(3)
+    mlp = tpx.Mlp(p, batch=16)
+    out = mlp.forward(torch.from_numpy(feat.view(np.int16)).cuda()).cpu().numpy()
+    rows = np.concatenate([np.arange(10), rng.choice(n, 300, replace=False), [65535, 65536, n - 1]])
+    ref, _ = L.forward(p, feat[rows])
+    rms = float(np.sqrt(np.mean(ref ** 2)))
+    assert np.abs(out[rows] - ref).max() <= REL_TOL * rms
+
+
+@pytest.mark.parametrize("n,seed", [(2, 1), (300, 2), (700, 3)])
+def test_gradients_match_oracle(tpx, orc, n, seed):
+    import torch
+    cl = synth.make_clusters(200 + seed, n)
+    hits, feat = _oracle_inputs(orc, cl)
+    p = _rand_params(seed)
+    T = L.targets(hits, cl["truth"])
+    # keep samples whose pair assignment is decided by a clear margin (the
+    # oracle's outputs); a near-tie may legitimately go either way
+    O, _ = L.forward(p, feat)
+    pa, pb = O[:, 0:3], O[:, 3:6]
+    c1 = ((pa - T[:, 0]) ** 2).sum(1) + ((pb - T[:, 1]) ** 2).sum(1)
+    c2 = ((pa - T[:, 1]) ** 2).sum(1) + ((pb - T[:, 0]) ** 2).sum(1)
+    ok = (cl["mult"] == 1) | (np.abs(c1 - c2) > 0.05 * (c1 + c2))
+    idx = np.nonzero(ok)[0]
+    loss_ref, g_ref, _ = L.grad(p, feat[idx], T[idx], cl["mult"][idx])
+    from paper_2603_04942_amd.learned import prepare
+    gfeat, ghits, gtruth, gmult = prepare(cl)
+    sel = torch.from_numpy(idx).cuda()
+    mlp = tpx.Mlp(p, batch=len(idx))
+    loss = mlp.grad(gfeat[sel].contiguous(), ghits[sel].contiguous(), gtruth[sel].contiguous(),
+                    gmult[sel].contiguous())
+    g = mlp.g.cpu().numpy().astype(np.float64)
+    assert abs(loss - loss_ref) <= REL_TOL * abs(loss_ref)
+    for name, a, b in zip([s for s, _ in L.SHAPES], L.unpack(g).values(), L.unpack(g_ref).values()):
+        r = _rel(a.ravel(), b.ravel())
+        _say(f"  grad {name}: rel {r:.2e}")
+        assert r <= REL_TOL, name
+
+
+def test_adam_matches_oracle(tpx):
+    import torch
+    rng = np.random.default_rng(4)
+    n = L.N_PARAM
+    p = rng.normal(0, 1, n).astype(np.float32)
+    m = rng.normal(0, 1e-2, n).astype(np.float32)
+    v = rng.uniform(0, 1e-3, n).astype(np.float32)
+    g = rng.normal(0, 1e-1, n).astype(np.float32)
+    ref_p, ref_m, ref_v = L.adam(p.astype(np.float64), m.astype(np.float64),
+                                 v.astype(np.float64), g.astype(np.float64), 7, 3e-3)
+    mlp = tpx.Mlp(p)
+    mlp.m.copy_(torch.from_numpy(m))
+    mlp.v.copy_(torch.from_numpy(v))
+    mlp.g.copy_(torch.from_numpy(g))
+    mlp.step = 6
+    mlp.adam(3e-3)
+    # fp32 rounds each product and sum within 2^-24 relative; the moments
+    # are sums of terms up to ~0.04 (m) and ~1e-3 (v) that can cancel, so
+    # the absolute bound is a few units of 2^-24 times those terms
+    assert np.allclose(mlp.p.cpu().numpy(), ref_p, rtol=1e-5, atol=1e-6)
+    assert np.allclose(mlp.m.cpu().numpy(), ref_m, rtol=1e-5, atol=2e-8)
+    assert np.allclose(mlp.v.cpu().numpy(), ref_v, rtol=1e-5, atol=2e-10)
+
+
+def test_refine_matches_oracle(tpx, orc):
+    import torch
+    cl = synth.make_clusters(9, 200)
+    hits, _ = _oracle_inputs(orc, cl)
+    from paper_2603_04942_amd.learned import prepare
+    _, ghits, _, _ = prepare(cl)
+    O = np.random.default_rng(2).normal(0, 1, (200, 8)).astype(np.float32)
+    R, p2 = L.refine(hits, O.astype(np.float64))
+    got = tpx.refine(ghits, torch.from_numpy(O).cuda()).cpu().numpy()
+    assert np.abs(got[:, 0:6].reshape(-1, 2, 3)[:, :, :2] - R[:, :, :2]).max() <= 1e-4
+    assert np.abs(got[:, 0:6].reshape(-1, 2, 3)[:, :, 2] - R[:, :, 2]).max() <= 2e-3
+    assert np.abs(got[:, 6] - p2).max() <= 1e-6
+
+
+def test_training_beats_weighted_centroid(tpx):
+    """Train from scratch on 120,000 generated clusters (30 % overlapping
+    pairs, sigma 0.5-2.5) and evaluate on 20,000 held-out ones: the network
+    must tell pairs from single hits, place the hits of pairs better than the
+    single weighted centroid can, and remove the time-walk bias of the
+    ToT-weighted time."""
+    import paper_2603_04942_amd.learned as LR
+    train = synth.make_clusters(31, 120_000)
+    test = synth.make_clusters(32, 20_000)
+    dtr = LR.prepare(train)
+    dte = LR.prepare(test)
+    mlp = tpx.Mlp(synth.init_mlp_params(1), batch=1024)
+    loss = LR.fit(mlp, dtr, epochs=6, lr=2e-3, lr_final=2e-4)
+    _say(f"final minibatch loss {loss:.4f}")
+    r = LR.predict(mlp, dte[0], dte[1]).cpu().numpy()
+    from paper_2603_04942_amd import hits_to_numpy
+    s = LR.score(hits_to_numpy(dte[1], dte[1].shape[0]), r, test["truth"], test["mult"])
+    _say(s)
+    assert s["multiplicity_accuracy"] >= 0.85
+    assert s["pair_pos_rmse_px"]["learned"] <= 0.8 * s["pair_pos_rmse_px"]["centroid"]
+    assert s["single_t_rmse_ns"]["learned"] <= 0.8 * s["single_t_rmse_ns"]["centroid"]
