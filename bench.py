@@ -271,7 +271,7 @@ def run_learned(args, pool, plain_hits_per_s):
     jobs = [(4003, b, min(blk, n_tr - b * blk)) for b in range((n_tr + blk - 1) // blk)]
     ejobs = [(4002, b, min(blk, args.learned_eval - b * blk))
              for b in range((args.learned_eval + blk - 1) // blk)]
-    mlp = tpx.Mlp(synth.init_mlp_params(4001), batch=args.learned_batch)
+    mlp = tpx.Mlp(synth.init_mlp_params(4001, zero_last=True), batch=args.learned_batch)
     lr0, lr1 = 2e-3, 1e-4
     t0 = time.perf_counter()
     train_s, seen, loss = 0.0, 0, None
@@ -295,7 +295,13 @@ def run_learned(args, pool, plain_hits_per_s):
     mult = np.concatenate([cl["mult"] for cl in test])
     n_ev = feat.shape[0]
     refined = LR.predict(mlp, feat, hits)
-    s = LR.score(tpx.hits_to_numpy(hits, n_ev), refined.cpu().numpy(), truth, mult)
+    hn = tpx.hits_to_numpy(hits, n_ev)
+    s = LR.score(hn, refined.cpu().numpy(), truth, mult)
+    # the network's own position for single hits, before the centroid is kept
+    raw = mlp.forward(feat).cpu().numpy().astype(np.float64)
+    one = mult == 1
+    d = (hn["x"] + raw[:, 0] - truth[:, 0, 0]) ** 2 + (hn["y"] + raw[:, 1] - truth[:, 0, 1]) ** 2
+    s["single_pos_rmse_px"]["network_raw"] = float(np.sqrt(np.mean(d[one])))
     # inference timing: patches + forward + refine over the held-out clusters
     cl0 = test[0]
     ev0 = tpx.to_device_events(cl0["events"])

@@ -277,8 +277,10 @@ void tpx_service_destroy(tpx_service* sv);
  * b2[256], W3[8][256], b3[8] (W as [out][in]); h1 = relu(W1 f + b1),
  * h2 = relu(W2 h1 + b2), o = W3 h2 + b3, with bfloat16 features, weights and
  * hidden activations on the matrix cores and fp32 accumulation and biases.
- * o[0..2] and o[3..5] are hits A and B as (x - cx, y - cy, (t - toa_first *
- * 1.5625 ns) / 10 ns), o[6] and o[7] the logits of one and two hits.
+ * o[0..2] and o[3..5] are hits A and B as corrections to the hit's weighted
+ * centroid (x - hit.x, y - hit.y, (t - toa_first * 1.5625 ns) / 10 ns), o[6]
+ * and o[7] the logits of one and two hits: all-zero outputs reproduce the
+ * weighted centroid.
  *   tpx_mlp_forward  out: fp32 [n][8]; ws: tpx_mlp_workspace_bytes(min(n,
  *                    65536)) bytes.
  *   tpx_mlp_grad     gradient of the mean loss over a batch of n samples into
@@ -294,7 +296,9 @@ void tpx_service_destroy(tpx_service* sv);
  *   tpx_mlp_adam     one Adam step (step counts from 1) on params with
  *                    moments m, v (fp32, zero at the start).
  *   tpx_mlp_refine   refined: fp32 [n][8] = absolute x, y, t_ns of hits A
- *                    and B, then the probability of two hits, then 0. */
+ *                    and B, then the probability p of two hits, then 0.  When
+ *                    p <= 1/2 (a single hit) x, y stay the weighted
+ *                    centroid's; t always comes from the network. */
 size_t tpx_patch_workspace_bytes(size_t n_hits);
 tpx_status tpx_patches(tpx_events ev, const uint32_t* labels, size_t n_ev, const tpx_hit* hits,
                        size_t n_hits, uint16_t* feat, void* ws, size_t ws_bytes, void* stream);

@@ -18,8 +18,10 @@ Plain numpy in float64, written from the definitions:
     row-major as [out][in] and the parameters packed W1, b1, W2, b2, W3, b3;
     here every product and sum is exact float64 and the hidden activations
     are not rounded;
-  * outputs o[0:3] and o[3:6] are two hits (x - cx, y - cy in pixels,
-    (t - ToA_first) / 10 ns), o[6] and o[7] the logits of one and two hits;
+  * outputs o[0:3] and o[3:6] are two hits as corrections to the weighted
+    centroid (x - xc, y - yc in pixels, with (xc, yc) the fp32 centroid, and
+    (t - ToA_first) / 10 ns), o[6] and o[7] the logits of one and two hits,
+    so a network that outputs zeros reproduces the weighted centroid;
   * the loss of a sample is the squared error of hit A for a single hit, the
     smaller of the two assignments' summed squared errors for a pair (ties
     take A-first / B-second), plus the cross entropy of the two logits;
@@ -124,14 +126,19 @@ def forward(params, feat_bits, quantize=True):
     return O, dict(X=X, W1=W1, W2=W2, W3=W3, Z1=Z1, H1=H1, Z2=Z2, H2=H2)
 
 
+def _centroid32(hits):
+    return (np.asarray(hits["x"], np.float32).astype(np.float64),
+            np.asarray(hits["y"], np.float32).astype(np.float64))
+
+
 def targets(hits, truth):
     """Targets [n, 2, 3] of the truth hits (absolute x, y in pixels, t in ns)
-    relative to each hit's patch centre and earliest ToA."""
-    cx, cy = centre(hits["x"], hits["y"])
+    relative to each hit's fp32 centroid and earliest ToA."""
+    xc, yc = _centroid32(hits)
     t0 = hits["toa_first"].astype(np.float64) * TICK_NS
     T = np.empty((len(hits), 2, 3))
-    T[:, :, 0] = truth[:, :, 0] - cx[:, None]
-    T[:, :, 1] = truth[:, :, 1] - cy[:, None]
+    T[:, :, 0] = truth[:, :, 0] - xc[:, None]
+    T[:, :, 1] = truth[:, :, 1] - yc[:, None]
     T[:, :, 2] = (truth[:, :, 2] - t0[:, None]) / T_UNIT_NS
     return T
 
@@ -191,13 +198,18 @@ def adam(params, m, v, g, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
 
 def refine(hits, O):
     """Absolute predictions: [n, 2, 3] (x, y in pixels, t in ns) and the
-    probability of two hits."""
-    cx, cy = centre(hits["x"], hits["y"])
+    probability of two hits; a cluster whose logit of two hits is not above
+    that of one keeps the weighted centroid's position (the network's
+    corrections apply to pairs), its time comes from the network."""
+    xc, yc = _centroid32(hits)
     t0 = hits["toa_first"].astype(np.float64) * TICK_NS
     R = np.empty((len(hits), 2, 3))
-    for k in range(2):
-        R[:, k, 0] = cx + O[:, 3 * k]
-        R[:, k, 1] = cy + O[:, 3 * k + 1]
-        R[:, k, 2] = t0 + T_UNIT_NS * O[:, 3 * k + 2]
     p2 = 1.0 / (1.0 + np.exp(O[:, 6] - O[:, 7]))
+    # a cluster judged single (logit of two not above that of one) keeps the
+    # centroid's position; the logits are compared as given
+    keep = (O[:, 7] > O[:, 6]).astype(np.float64)
+    for k in range(2):
+        R[:, k, 0] = xc + keep * O[:, 3 * k]
+        R[:, k, 1] = yc + keep * O[:, 3 * k + 1]
+        R[:, k, 2] = t0 + T_UNIT_NS * O[:, 3 * k + 2]
     return R, p2

@@ -5,8 +5,9 @@
 // The patch of a hit is centred on the pixel nearest to its ToT-weighted
 // centroid (Sec. V, Centroiding, Eq. 9); plane 0 holds the summed ToT of each
 // pixel / 1024, plane 1 its earliest ToA minus the hit's earliest ToA in
-// 64-tick (100 ns) units.  Outputs: two hits (x - cx, y - cy, (t - ToA_first)
-// / 10 ns) and the logits of one and two hits.
+// 64-tick (100 ns) units.  Outputs: two hits as corrections to the weighted
+// centroid (x - xc, y - yc, (t - ToA_first) / 10 ns) and the logits of one and
+// two hits; a network that outputs zeros reproduces the weighted centroid.
 //
 // Layout.  Parameters are one fp32 array packed W1[256][98], b1[256],
 // W2[256][256], b2[256], W3[8][256], b3[8] (W as [out][in]).  Features are
@@ -179,20 +180,19 @@ __global__ void k_zero_f32(float* p, int n) {
     if ((int)threadIdx.x < n) p[threadIdx.x] = 0.f;
 }
 
-// one thread per sample: targets relative to the patch centre and earliest
-// ToA, the loss (pair matched the cheaper way round, ties A-first), dL/dO / n
+// one thread per sample: targets relative to the weighted centroid and the
+// earliest ToA, the loss (pair matched the cheaper way round, ties A-first), dL/dO / n
 __global__ void k_loss(const float* O, const tpx_hit* hits, const float* truth,
                        const uint8_t* mult, int n, float* G32, uint16_t* G16, float* loss_sum) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     float li = 0.f;
     if (i < n) {
         const tpx_hit& h = hits[i];
-        const float cx = (float)centre_of(h.x), cy = (float)centre_of(h.y);
         const double t0 = (double)h.toa_first * 1.5625;
         float T[2][3];
         for (int k = 0; k < 2; ++k) {
-            T[k][0] = truth[i * 6 + 3 * k + 0] - cx;
-            T[k][1] = truth[i * 6 + 3 * k + 1] - cy;
+            T[k][0] = truth[i * 6 + 3 * k + 0] - h.x;
+            T[k][1] = truth[i * 6 + 3 * k + 1] - h.y;
             T[k][2] = (float)(((double)truth[i * 6 + 3 * k + 2] - t0) / 10.0);
         }
         float o[8];
@@ -261,14 +261,17 @@ __global__ void k_refine(const tpx_hit* hits, const float* O, uint64_t n, float*
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const tpx_hit& h = hits[i];
-    const float cx = (float)centre_of(h.x), cy = (float)centre_of(h.y);
     const double t0 = (double)h.toa_first * 1.5625;
+    const float p2 = 1.f / (1.f + expf(O[i * 8 + 6] - O[i * 8 + 7]));
+    // a cluster judged single (logit of two not above that of one) keeps the
+    // weighted centroid's position
+    const float keep = O[i * 8 + 7] > O[i * 8 + 6] ? 1.f : 0.f;
     for (int k = 0; k < 2; ++k) {
-        out[i * 8 + 3 * k + 0] = cx + O[i * 8 + 3 * k + 0];
-        out[i * 8 + 3 * k + 1] = cy + O[i * 8 + 3 * k + 1];
+        out[i * 8 + 3 * k + 0] = h.x + keep * O[i * 8 + 3 * k + 0];
+        out[i * 8 + 3 * k + 1] = h.y + keep * O[i * 8 + 3 * k + 1];
         out[i * 8 + 3 * k + 2] = (float)(t0 + 10.0 * (double)O[i * 8 + 3 * k + 2]);
     }
-    out[i * 8 + 6] = 1.f / (1.f + expf(O[i * 8 + 6] - O[i * 8 + 7]));
+    out[i * 8 + 6] = p2;
     out[i * 8 + 7] = 0.f;
 }
 

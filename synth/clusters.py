@@ -99,15 +99,18 @@ MLP_SHAPES = [((256, 98), 98), ((256,), 0), ((256, 256), 256), ((256,), 0), ((8,
               ((8,), 0)]
 
 
-def init_mlp_params(seed):
+def init_mlp_params(seed, zero_last=False):
     """Initial parameters of the 98 -> 256 -> 256 -> 8 network, packed
     W1, b1, W2, b2, W3, b3 with W as [out][in]: He-uniform weights
     (U(-sqrt(6 / fan_in), +sqrt(6 / fan_in))), zero biases, from PCG64(seed),
-    as float32."""
+    as float32; zero_last leaves the output layer at zero."""
     rng = np.random.default_rng(seed)
     parts = []
-    for shape, fan_in in MLP_SHAPES:
-        if fan_in:
+    for k, (shape, fan_in) in enumerate(MLP_SHAPES):
+        if fan_in and zero_last and k == 4:
+            rng.uniform(-1, 1, shape)
+            parts.append(np.zeros(shape).ravel())
+        elif fan_in:
             lim = math.sqrt(6.0 / fan_in)
             parts.append(rng.uniform(-lim, lim, shape).ravel())
         else:

@@ -199,5 +199,16 @@ def test_targets_and_refine_invert():
     T = L.targets(h, truth)
     O = np.zeros((n, 8))
     O[:, 0:3], O[:, 3:6] = T[:, 0], T[:, 1]
+    O[:, 7] = 1.0                               # judged a pair: corrections apply
     R, p2 = L.refine(h, O)
-    assert np.allclose(R, truth, atol=1e-9) and np.allclose(p2, 0.5)
+    assert np.allclose(R, truth, atol=1e-9) and np.all(p2 > 0.5)
+    # judged single: the centroid's position, the network's time
+    O[:, 7] = -1.0
+    R1, _ = L.refine(h, O)
+    assert np.array_equal(R1[:, :, 0], np.repeat(h["x"].astype(np.float64)[:, None], 2, 1))
+    assert np.allclose(R1[:, :, 2], truth[:, :, 2], atol=1e-9)
+    # zero outputs are the weighted centroid itself (the fallback)
+    R0, _ = L.refine(h, np.zeros((n, 8)))
+    assert np.array_equal(R0[:, 0, 0], h["x"].astype(np.float64))
+    assert np.array_equal(R0[:, 1, 1], h["y"].astype(np.float64))
+    assert np.array_equal(R0[:, 0, 2], h["toa_first"] * 1.5625)
