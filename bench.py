@@ -337,6 +337,44 @@ def run_learned(args, pool, plain_hits_per_s):
         plain_path_hits_per_s=plain_hits_per_s, score=s)
 
 
+def run_uneven(args, w):
+    """The uneven-shot workload (c3: mixture of Poisson(5), Poisson(40) and
+    Poisson(200) hits per shot, electron- and ion-like spots): the segment
+    stride is chosen by tpx_stream_autotune on the whole stream, then the
+    stream step is timed at that stride like the c2 step."""
+    import torch
+
+    import paper_2603_04942_amd as tpx
+
+    pk = torch.from_numpy(w.packets.view(np.int64)).cuda()
+    n = pk.numel()
+    s = tpx.Stream(n, pix_epoch0=w.pix_epoch0, tdc_epoch0=w.tdc_epoch0)
+    cap = n // 4 + 1024
+    hits = torch.empty((cap, 48), dtype=torch.uint8, device="cuda")
+    best, sweep = s.autotune(pk, True, args.strides, hits, cap, reps=2)
+    fresh = s.get_state()
+    reps = max(1, args.steps // 2)
+    for _ in range(2):
+        s.set_state(fresh)
+        rc, nh, st = s.process_raw(pk, True, hits, cap)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        s.set_state(fresh)
+        rc, nh, st = s.process_raw(pk, True, hits, cap)
+        if rc != 0:
+            raise tpx.TpxError(rc, "tpx_process_stream", s.lib.tpx_last_error().decode())
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    s.close()
+    return dict(workload="c3: 200,000 shots, hits/shot 0.7 Poisson(5) + 0.25 Poisson(40) + "
+                         "0.05 Poisson(200); 60% sigma 0.5 px, 40% sigma U(1.5, 2.5) px with ToT "
+                         "scale up to 1023",
+                packets=int(n), events=int(st.n_events), hits=int(nh),
+                stride_sweep_ms=sweep, stride=best, ms_per_step=ms,
+                events_per_s=st.n_events / (ms * 1e-3))
+
+
 def run_paper_mode(args, wl):
     """The paper's local-maximum hits (tpx_local_maxima) on the decoded c2
     events: events resident in HBM, HIP-event timing on the call's stream."""
@@ -404,6 +442,9 @@ def main():
     ap.add_argument("--latency-speeds", type=float, nargs="+", default=[1.0, 10.0, 200.0],
                     help="paced replay speedups over acquisition")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-uneven", action="store_true")
+    ap.add_argument("--strides", type=int, nargs="+", default=[128, 256, 512, 1024, 1536, 2048],
+                    help="segment strides the autotuner tries on the uneven-shot workload")
     ap.add_argument("--learned-train", type=int, default=10_000_000,
                     help="training clusters (learned centroider)")
     ap.add_argument("--learned-eval", type=int, default=1_000_000, help="held-out clusters")
@@ -429,6 +470,11 @@ def main():
     t = time.perf_counter()
     wl = synth.make_config("c2", n_shots=args.shots, with_truth=False, workers=args.workers)
     log(f"generated c2: {wl.n_packets} packets in {time.perf_counter() - t:.1f} s")
+    wl3 = None
+    if not args.no_uneven:
+        t = time.perf_counter()
+        wl3 = synth.make_config("c3", with_truth=False, workers=args.workers)
+        log(f"generated c3: {wl3.n_packets} packets in {time.perf_counter() - t:.1f} s")
     ms, stages, stats = run_gpu(args, wl)
     log(f"gpu: {ms:.3f} ms/step, stages {json.dumps({k: round(v, 4) for k, v in stages.items()})}")
     n_ev, n_hits, n_pk = stats["n_events"], stats["n_hits"], wl.n_packets
@@ -481,6 +527,10 @@ def main():
         "hits_per_s": n_hits / (ms * 1e-3),
         "acquisition_multiple": value / (n_ev / (args.shots * 1e-3)),
     }
+    if not args.no_uneven:
+        out["uneven"] = run_uneven(args, wl3)
+        del wl3
+        log(f"uneven: {out['uneven']}")
     if not args.no_paper_mode:
         out["paper_mode"] = run_paper_mode(args, wl)
         log(f"paper mode: {out['paper_mode']}")

@@ -221,6 +221,23 @@ tpx_status tpx_stream_get_timing(const tpx_stream* s, float* ms_h, size_t n,
                                  size_t* n_stages_h);
 const char* tpx_stream_stage_name(size_t i);
 
+/* Segment stride of the stream's clustering: consecutive shots are packed
+ * into segments that start every q kept events (a segment ends at the end of
+ * the shot that crosses the next start), one workgroup per segment; 64 <= q
+ * <= 2048, default 1024.  Results do not depend on q, only the time.
+ * tpx_stream_autotune (the sweep of the uneven-shot workload) runs the chunk
+ * at every candidate q (best of `reps`, timed with HIP events on `stream`),
+ * restoring the stream state before each run and after the last, writes the
+ * times to ms_h (host, n_cand, may be NULL) and keeps the fastest q
+ * (*best_h).  hits / hit_cap as in tpx_process_stream; on an error the
+ * stream keeps its state and its former q. */
+tpx_status tpx_stream_set_segment(tpx_stream* s, uint32_t q);
+uint32_t tpx_stream_get_segment(const tpx_stream* s);
+tpx_status tpx_stream_autotune(tpx_stream* s, const uint64_t* chunk, size_t n_pkts, int flush,
+                               tpx_hit* hits, size_t hit_cap, const uint32_t* cand_h,
+                               size_t n_cand, int reps, float* ms_h, uint32_t* best_h,
+                               void* stream);
+
 /* Continuous batching over one stream (the streaming workload's chunked
  * acquisition, Sec. IV: the unwrap runs across the whole stream).  Chunks are
  * admitted into a device ring as they arrive; every run processes all whole

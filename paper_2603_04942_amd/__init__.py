@@ -71,7 +71,8 @@ EXPORTS = ("tpx_params_default", "tpx_unwrap_state_init", "tpx_workspace_bytes",
            "tpx_stream_set_timing", "tpx_stream_get_timing", "tpx_stream_stage_name",
            "tpx_service_create", "tpx_service_submit", "tpx_service_run", "tpx_service_destroy",
            "tpx_patch_workspace_bytes", "tpx_patches", "tpx_mlp_workspace_bytes",
-           "tpx_mlp_forward", "tpx_mlp_grad", "tpx_mlp_adam", "tpx_mlp_refine")
+           "tpx_mlp_forward", "tpx_mlp_grad", "tpx_mlp_adam", "tpx_mlp_refine",
+           "tpx_stream_set_segment", "tpx_stream_get_segment", "tpx_stream_autotune")
 
 _lib = None
 
@@ -118,6 +119,12 @@ def load(path=LIB_PATH):
     lib.tpx_mlp_refine.argtypes = [P, P, S, P, P]
     for f in ("tpx_patches", "tpx_mlp_forward", "tpx_mlp_grad", "tpx_mlp_adam", "tpx_mlp_refine"):
         getattr(lib, f).restype = I
+    lib.tpx_stream_set_segment.argtypes = [P, ctypes.c_uint32]
+    lib.tpx_stream_set_segment.restype = I
+    lib.tpx_stream_get_segment.argtypes = [P]
+    lib.tpx_stream_get_segment.restype = ctypes.c_uint32
+    lib.tpx_stream_autotune.argtypes = [P, P, S, ctypes.c_int, P, S, P, S, ctypes.c_int, P, P, P]
+    lib.tpx_stream_autotune.restype = I
     lib.tpx_status_str.argtypes = [I]
     lib.tpx_status_str.restype = ctypes.c_char_p
     lib.tpx_last_error.argtypes = []
@@ -358,6 +365,25 @@ class Stream:
             raise TpxError(rc, "tpx_process_stream", f"need {n} hits")
         _check(rc, "tpx_process_stream")
         return hits_to_numpy(hits, n), st.as_dict()
+
+    def set_segment(self, q):
+        _check(self.lib.tpx_stream_set_segment(self.h, int(q)), "tpx_stream_set_segment")
+
+    def segment(self):
+        return int(self.lib.tpx_stream_get_segment(self.h))
+
+    def autotune(self, chunk, flush, candidates, hits, hit_cap, reps=3):
+        """tpx_stream_autotune: (best stride, {stride: ms})."""
+        torch = self.torch
+        pk = _u64(torch, chunk)
+        cand = (ctypes.c_uint32 * len(candidates))(*candidates)
+        ms = (ctypes.c_float * len(candidates))()
+        best = ctypes.c_uint32()
+        rc = self.lib.tpx_stream_autotune(self.h, _ptr(pk), pk.numel(), int(flush), _ptr(hits),
+                                          hit_cap, cand, len(candidates), reps, ms,
+                                          ctypes.byref(best), _stream(torch))
+        _check(rc, "tpx_stream_autotune")
+        return int(best.value), {int(c): float(m) for c, m in zip(candidates, ms)}
 
     def get_state(self):
         n = ctypes.c_size_t()

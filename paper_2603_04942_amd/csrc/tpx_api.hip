@@ -38,7 +38,8 @@ namespace {
         if (e_ != hipSuccess) return fail(TPX_EHIP, "%s: %s", #x, hipGetErrorString(e_)); \
     } while (0)
 
-constexpr uint32_t kQ = 1024;           // segment stride (events)
+constexpr uint32_t kQ = 1024;           // segment stride (events), default
+constexpr uint32_t kQMin = 64, kQMax = 2048;  // strides a stream accepts
 constexpr uint32_t kQPaper = 512;       // segment stride of the paper mode: a shot of up to
                                         // 1,536 events always fits one 2,048-event segment
 constexpr int kStages = 7;              // timed stages of the stream fast path
@@ -528,6 +529,7 @@ struct tpx_stream {
     uint32_t carry_rebase;  // subtract from c_shot[cur] to get window indices
     uint64_t carry_last1;   // window index of the last carried event + 1 (0 = none)
     int cur;
+    uint32_t q;             // segment stride of the clustering (events)
     uint64_t n_fallback;    // chunks that needed the general (sorting) path
     // optional per-stage timing with HIP events on the caller's stream
     int timing;
@@ -560,7 +562,7 @@ void free_stream(tpx_stream* s) {
 
 ClusterArgs stream_cluster_args(tpx_stream* s, tpx_hit* hits, uint64_t hit_cap) {
     ClusterArgs a{};
-    a.q = kQ;
+    a.q = s->q;
     a.dxy = s->p.dxy;
     a.dt = s->p.dt_ticks;
     a.carry_gidx = s->c_gidx[s->cur];
@@ -653,9 +655,9 @@ tpx_status stream_fast(tpx_stream* s, const uint64_t* chunk, uint64_t n, int flu
     c.n_grp_dev = &s->res->n_close_grp;
     c.skip = &s->res->unsorted;
     c.seg_lo = s->seg_lo;
-    launch_seg_table(c.grp_off, c.n_grp_dev, c.n_ev_dev, c.skip, kQ, rows, s->seg_lo, s->res, hs);
+    launch_seg_table(c.grp_off, c.n_grp_dev, c.n_ev_dev, c.skip, s->q, rows, s->seg_lo, s->res, hs);
     mark(s, 4, hs);
-    const uint64_t grid = cluster_grid(s->n_carry + n, kQ);
+    const uint64_t grid = cluster_grid(s->n_carry + n, s->q);
     launch_cluster(c, false, grid, hs);
     mark(s, 5, hs);
     launch_scan_u32(s->seg_cnt, s->seg_off, 0, &s->res->n_seg, s->block_tmp, hs);
@@ -704,8 +706,8 @@ tpx_status stream_general(tpx_stream* s, const uint64_t* chunk, uint64_t n, int 
     c.n_ev_dev = &s->res->n_close_ev;
     c.n_grp_dev = &s->res->n_close_list;
     c.seg_lo = s->seg_lo;
-    launch_seg_table(c.grp_off, c.n_grp_dev, c.n_ev_dev, nullptr, kQ, N, s->seg_lo, s->res, hs);
-    const uint64_t grid = cluster_grid(N, kQ);
+    launch_seg_table(c.grp_off, c.n_grp_dev, c.n_ev_dev, nullptr, s->q, N, s->seg_lo, s->res, hs);
+    const uint64_t grid = cluster_grid(N, s->q);
     launch_cluster(c, false, grid, hs);
     launch_scan_u32(s->seg_cnt, s->seg_off, 0, &s->res->n_seg, s->block_tmp, hs);
     launch_seg_centroid(c, grid, hs);
@@ -733,7 +735,8 @@ tpx_status tpx_stream_create(const tpx_params* p_h, size_t max_chunk_pkts, tpx_s
     s->carry_cap = n;
     s->ev_cap = n + s->carry_cap;
     s->tab_cap = n + s->carry_cap + 2;
-    s->seg_cap = s->ev_cap / kQ + 4;
+    s->q = kQ;
+    s->seg_cap = s->ev_cap / kQMin + 4;
     if (hipHostMalloc((void**)&s->res_h, sizeof(DevResults), 0) != hipSuccess) {
         (void)hipGetLastError();
         s->res_h = nullptr;
@@ -975,5 +978,76 @@ tpx_status tpx_stream_get_timing(const tpx_stream* s, float* ms_h, size_t n, siz
 }
 
 const char* tpx_stream_stage_name(size_t i) { return i < (size_t)kStages ? kStageNames[i] : ""; }
+
+tpx_status tpx_stream_set_segment(tpx_stream* s, uint32_t q) {
+    if (!s) return fail(TPX_EINVAL, "stream is NULL");
+    if (q < kQMin || q > kQMax)
+        return fail(TPX_EINVAL, "segment stride %u outside [%u, %u]", q, kQMin, kQMax);
+    s->q = q;
+    return TPX_OK;
+}
+
+uint32_t tpx_stream_get_segment(const tpx_stream* s) { return s ? s->q : 0; }
+
+// Times the chunk at every candidate stride (best of `reps`, HIP events on
+// the call's stream), restoring the stream state before every run; keeps the
+// fastest stride and leaves the stream state as it was.
+tpx_status tpx_stream_autotune(tpx_stream* s, const uint64_t* chunk, size_t n_pkts, int flush,
+                               tpx_hit* hits, size_t hit_cap, const uint32_t* cand_h,
+                               size_t n_cand, int reps, float* ms_h, uint32_t* best_h,
+                               void* stream) {
+    if (!s || !cand_h || !best_h) return fail(TPX_EINVAL, "NULL argument");
+    if (n_cand == 0 || reps < 1) return fail(TPX_EINVAL, "no candidates or repetitions");
+    for (size_t i = 0; i < n_cand; ++i)
+        if (cand_h[i] < kQMin || cand_h[i] > kQMax)
+            return fail(TPX_EINVAL, "segment stride %u outside [%u, %u]", cand_h[i], kQMin, kQMax);
+    size_t bytes = 0;
+    tpx_status rc = tpx_stream_get_state(s, nullptr, &bytes);
+    if (rc) return rc;
+    std::vector<uint8_t> saved(bytes);
+    if ((rc = tpx_stream_get_state(s, saved.data(), &bytes))) return rc;
+    const uint32_t q0 = s->q;
+    const uint64_t fb0 = s->n_fallback;
+    hipStream_t hs = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(TPX_EHIP, "event creation failed");
+    }
+    float best = 3.0e38f;
+    uint32_t best_q = q0;
+    for (size_t i = 0; i < n_cand && rc == TPX_OK; ++i) {
+        s->q = cand_h[i];
+        float t_min = 3.0e38f;
+        for (int r = 0; r < reps && rc == TPX_OK; ++r) {
+            if ((rc = tpx_stream_set_state(s, saved.data(), bytes))) break;
+            size_t nh = 0;
+            float ms = 0.f;
+            if (hipEventRecord(e0, hs) != hipSuccess) rc = fail(TPX_EHIP, "event record failed");
+            if (!rc) rc = tpx_process_stream(s, chunk, n_pkts, flush, hits, hit_cap, &nh, nullptr,
+                                             stream);
+            if (!rc && (hipEventRecord(e1, hs) != hipSuccess ||
+                        hipEventSynchronize(e1) != hipSuccess ||
+                        hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                rc = fail(TPX_EHIP, "event timing failed");
+            if (!rc) t_min = std::min(t_min, ms);
+        }
+        if (ms_h) ms_h[i] = t_min;
+        if (!rc && t_min < best) {
+            best = t_min;
+            best_q = cand_h[i];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    const tpx_status rs = tpx_stream_set_state(s, saved.data(), bytes);
+    s->n_fallback = fb0;
+    s->q = rc ? q0 : best_q;
+    if (rc) return rc;
+    if (rs) return rs;
+    *best_h = best_q;
+    return TPX_OK;
+}
 
 }  // extern "C"
