@@ -53,13 +53,18 @@ def stage_bytes(n_packets, n_events, n_hits):
     }
 
 
+KERNEL_SOURCES = ("tpx_decode.hip", "tpx_cluster.hip", "tpx_util.hip", "tpx_internal.h",
+                  "tpx_kernels.h")
+
+
 def source_digest():
-    """sha256 over the library sources and header: HBM traffic counters are
-    only reported while the code they were taken on is unchanged."""
+    """sha256 over the sources that define and launch the stream path's
+    kernels: HBM traffic counters are only reported while the code they were
+    taken on is unchanged."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2603_04942_amd", "csrc")
-    files = sorted(os.path.join(csrc, f) for f in os.listdir(csrc) if f.endswith((".hip", ".h")))
+    files = [os.path.join(csrc, f) for f in KERNEL_SOURCES]
     for f in files + [os.path.join(ROOT, "include", "tpx.h")]:
         with open(f, "rb") as fh:
             h.update(os.path.basename(f).encode() + b"\0" + fh.read())
