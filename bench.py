@@ -203,10 +203,13 @@ def run_latency(args):
 
 
 def batched_replays(args, tpx, w, pk, chunk, pk_rate):
-    """Paced replays through tpx_service: chunk k is admitted when released;
-    each run takes every chunk admitted so far (up to the batch limit), so
-    when chunks arrive faster than one call per chunk can finish, several go
-    into one call.  Latency of a chunk = completion of its run - release."""
+    """Paced replays through tpx_service: a producer thread admits chunk k when
+    it is released (its copy goes on the service's own stream and overlaps
+    the batch in flight); the main thread runs the service in a loop, each run
+    taking every chunk admitted so far (up to the batch limit).  Latency of a
+    chunk = completion of the run that took it - its release."""
+    import threading
+
     import torch
 
     n_pk = pk.numel()
@@ -218,35 +221,52 @@ def batched_replays(args, tpx, w, pk, chunk, pk_rate):
     for speed in args.latency_speeds:
         lim = max(1, min(len(starts), int(2.0 * pk_rate * speed / chunk)))
         sv = tpx.Service(max_batch, pix_epoch0=w.pix_epoch0, tdc_epoch0=w.tdc_epoch0)
-        t0 = time.perf_counter()
+        views = [pk[a:a + chunk] for a in starts[:lim]]
+        t0 = time.perf_counter() + 0.01
         rel = [t0 + min(a + chunk, n_pk) / pk_rate / speed for a in starts[:lim]]
-        nxt = done = runs = 0
-        pending, lat = [], []
-        while done < lim:
-            if nxt < lim and not pending:
-                while time.perf_counter() < rel[nxt]:
-                    pass
-            while nxt < lim and time.perf_counter() >= rel[nxt]:
-                a = starts[nxt]
-                rc = sv.lib.tpx_service_submit(sv.h, tpx._ptr(pk[a:a + chunk]),
-                                               min(chunk, n_pk - a), 1, None,
-                                               tpx._stream(torch))
-                if rc == tpx.ECAPACITY:
-                    break
-                if rc != 0:
-                    raise tpx.TpxError(rc, "tpx_service_submit", sv.lib.tpx_last_error().decode())
-                pending.append(rel[nxt])
-                nxt += 1
-            rc, nh, nd, st = sv.run_raw(nxt == lim, hits, cap)
+        done = threading.Event()
+        errors = []
+
+        def producer():
+            try:
+                for k in range(lim):
+                    # sleep (releasing the interpreter lock) until the release
+                    wait = rel[k] - time.perf_counter()
+                    if wait > 0:
+                        time.sleep(wait)
+                    while True:
+                        rc = sv.lib.tpx_service_submit(sv.h, tpx._ptr(views[k]), views[k].numel(),
+                                                       1, None, tpx._stream(torch))
+                        if rc != tpx.ECAPACITY:
+                            break
+                    if rc != 0:
+                        raise tpx.TpxError(rc, "tpx_service_submit",
+                                           sv.lib.tpx_last_error().decode())
+            except Exception as e:  # noqa: BLE001 - re-raised below
+                errors.append(e)
+            finally:
+                done.set()
+
+        th = threading.Thread(target=producer)
+        switch = sys.getswitchinterval()
+        sys.setswitchinterval(1e-4)   # hand the interpreter lock over quickly
+        th.start()
+        lat, done_n, runs = [], 0, 0
+        while done_n < lim and not errors:
+            fin = done.is_set()
+            rc, nh, nd, st = sv.run_raw(fin, hits, cap)
             t = time.perf_counter()
             if rc != 0:
-                raise tpx.TpxError(rc, "tpx_service_run", sv.lib.tpx_last_error().decode())
-            k = nd - done
-            lat += [(t - r) * 1e3 for r in pending[:k]]
-            pending = pending[k:]
-            done = nd
-            runs += 1
+                errors.append(tpx.TpxError(rc, "tpx_service_run", sv.lib.tpx_last_error().decode()))
+                break
+            lat += [(t - rel[k]) * 1e3 for k in range(done_n, nd)]
+            runs += nd > done_n
+            done_n = nd
+        th.join()
+        sys.setswitchinterval(switch)
         sv.close()
+        if errors:
+            raise errors[0]
         res[f"{speed:g}x"] = dict(chunks=lim, runs=runs, p50_ms=float(np.percentile(lat, 50)),
                                   p99_ms=float(np.percentile(lat, 99)))
     del hits

@@ -248,19 +248,24 @@ tpx_status tpx_stream_autotune(tpx_stream* s, const uint64_t* chunk, size_t n_pk
  *   tpx_service_create  max_batch_pkts: largest batch (and chunk); ring_pkts
  *                       >= max_batch_pkts: admission capacity.  Allocates the
  *                       ring, a staging buffer and a tpx_stream.
- *   tpx_service_submit  copies n_pkts words (device memory when
- *                       chunk_on_device, else host) into the ring,
- *                       asynchronously on `stream`; *seq_h = the chunk's
- *                       number (0, 1, ...).  TPX_EINVAL when n_pkts >
- *                       max_batch_pkts, TPX_ECAPACITY when the ring is full
- *                       (run first); the service is then unchanged.
+ *   tpx_service_submit  reserves ring space and copies n_pkts words (device
+ *                       memory when chunk_on_device, else host) into it on
+ *                       the service's own stream, after the work already on
+ *                       `stream` (which may still be writing the chunk);
+ *                       *seq_h = the chunk's number (0, 1, ...).  TPX_EINVAL
+ *                       when n_pkts > max_batch_pkts, TPX_ECAPACITY when the
+ *                       ring is full (the words of unprocessed chunks and of
+ *                       the batch in flight stay reserved); the service is
+ *                       then unchanged.
  *   tpx_service_run     one batch: hits of the shots it closes (all shots when
  *                       flush and the batch holds every admitted chunk) as in
  *                       tpx_process_stream; *n_done_h = chunks processed so
  *                       far.  With nothing admitted it still flushes.  On an
- *                       error the batch stays admitted.  Synchronises
- *                       `stream`.
- * Calls on one service must not overlap. */
+ *                       error the batch stays admitted.  The batch's copies
+ *                       are waited for on the device.  Synchronises `stream`.
+ * One host thread may submit while another runs: the admission copies of new
+ * chunks then overlap the batch on the GPU.  Apart from that pair, calls on
+ * one service must not overlap. */
 typedef struct tpx_service tpx_service;
 tpx_status tpx_service_create(const tpx_params* p_h, size_t max_batch_pkts, size_t ring_pkts,
                               tpx_service** out_h);

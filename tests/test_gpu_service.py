@@ -135,3 +135,63 @@ def test_errors_leave_the_service_unchanged(tpx, c5):
     finally:
         sv.close()
     assert_hits_match(np.concatenate([h1, h2]), ref)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_submit_from_another_thread_while_running(tpx, c5, seed):
+    """A producer thread admits chunks (host and device memory, a small ring
+    that fills and wraps) while the main thread runs batches: the copies of
+    new chunks overlap the batch on the GPU, and the hits equal the whole
+    stream's."""
+    import threading
+    import time
+
+    import torch
+    w, ref, rst = c5
+    rng = np.random.default_rng(5100 + seed)
+    cuts = np.sort(rng.choice(np.arange(1, w.n_packets), int(rng.integers(10, 60)), replace=False))
+    chunks = np.split(w.packets, cuts)
+    dev = [torch.from_numpy(c.view(np.int64)).cuda() if k % 2 else c for k, c in enumerate(chunks)]
+    torch.cuda.synchronize()
+    max_batch = int(max(c.size for c in chunks) * 3)
+    sv = tpx.Service(max_batch, int(max_batch * 1.5), pix_epoch0=w.pix_epoch0,
+                     tdc_epoch0=w.tdc_epoch0)
+    done = threading.Event()
+    errors = []
+
+    def producer():
+        try:
+            for c in dev:
+                while True:
+                    try:
+                        sv.submit(c)
+                        break
+                    except tpx.TpxError as e:
+                        if e.rc != tpx.ECAPACITY:
+                            raise
+                        time.sleep(1e-4)
+        except Exception as e:  # noqa: BLE001 - reported by the main thread
+            errors.append(e)
+        finally:
+            done.set()
+
+    t = threading.Thread(target=producer)
+    out, n_ev, runs = [], 0, 0
+    try:
+        t.start()
+        while True:
+            fin = done.is_set()
+            h, nd, st = sv.run(flush=fin, hit_cap=1 << 16)
+            out.append(h)
+            n_ev += st["n_events"]
+            runs += 1
+            if (fin and nd == len(chunks)) or errors:
+                break
+            assert runs < 100_000
+    finally:
+        t.join()
+        sv.close()
+    assert not errors, errors
+    _say(f"  threaded: {len(chunks)} chunks in {runs} runs")
+    assert n_ev == rst["n_events"]
+    assert_hits_match(np.concatenate(out), ref)
