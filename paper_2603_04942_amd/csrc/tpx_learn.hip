@@ -104,56 +104,102 @@ struct Gemm {
     int64_t ldc16;
 };
 
-constexpr int kTM = 64, kTN = 64, kTK = 32, kPitch = kTK + 8;
+constexpr int kTM = 64, kTK = 32, kPitch = kTK + 8;
 
-// 256 threads = 4 waves in 2 x 2; each wave owns a 32 x 32 block of the
-// 64 x 64 tile as 2 x 2 MFMA 16x16x16 blocks.  Operand layout of the MFMA:
-// lane l holds A[l % 16][4 (l / 16) .. +3] and B[4 (l / 16) .. +3][l % 16];
-// result lane l holds C[4 (l / 16) + r][l % 16], r = 0..3.
+// Loads a rows x 32 tile of a strided operand into LDS as [row][k].  When k
+// is contiguous (stride 1) and K is a multiple of the vector width, each
+// thread moves `vec` consecutive k at once (a vector of 2 or 4 bfloat16);
+// otherwise one element at a time, with consecutive threads along whichever
+// of row / k is contiguous.
+template <int kRows, int vec>
+__device__ __forceinline__ void load_tile(uint16_t (*T)[kPitch], const uint16_t* src, int64_t s_row,
+                                          int64_t s_k, int row0, int n_rows, int k0, int K,
+                                          int tid) {
+    // trip counts are compile-time constants (kRows * 32 / vec is a multiple
+    // of 256), so every load of a tile is issued before the first wait
+    static_assert((kRows * kTK / 4) % 256 == 0, "tile rows must be a multiple of 32");
+    if constexpr (vec == 4) {
+#pragma unroll
+        for (int it = 0; it < kRows * kTK / 4 / 256; ++it) {
+            const int e = tid + 256 * it;
+            const int r = e >> 3, k = (e & 7) * 4;
+            const int gr = row0 + r, gk = k0 + k;
+            uint2 v = make_uint2(0u, 0u);
+            if (gr < n_rows && gk < K) v = *(const uint2*)(src + gr * s_row + gk);
+            *(uint2*)&T[r][k] = v;
+        }
+    } else if constexpr (vec == 2) {
+#pragma unroll
+        for (int it = 0; it < kRows * kTK / 2 / 256; ++it) {
+            const int e = tid + 256 * it;
+            const int r = e >> 4, k = (e & 15) * 2;
+            const int gr = row0 + r, gk = k0 + k;
+            uint32_t v = 0u;
+            if (gr < n_rows && gk < K) v = *(const uint32_t*)(src + gr * s_row + gk);
+            *(uint32_t*)&T[r][k] = v;
+        }
+    } else {
+        const bool k_contig = s_k == 1;
+#pragma unroll
+        for (int it = 0; it < kRows * kTK / 256; ++it) {
+            const int e = tid + 256 * it;
+            const int r = k_contig ? e >> 5 : e % kRows;
+            const int k = k_contig ? e & 31 : e / kRows;
+            const int gr = row0 + r, gk = k0 + k;
+            T[r][k] = (gr < n_rows && gk < K) ? src[gr * s_row + gk * s_k] : (uint16_t)0;
+        }
+    }
+}
+
+// vector width for a k-contiguous operand: every row start and K aligned
+__host__ inline int vec_width(const uint16_t* p, int64_t s_row, int64_t s_k, int K) {
+    if (s_k != 1) return 1;
+    const uintptr_t a = (uintptr_t)p;
+    if (K % 4 == 0 && s_row % 4 == 0 && a % 8 == 0) return 4;
+    if (K % 2 == 0 && s_row % 2 == 0 && a % 4 == 0) return 2;
+    return 1;
+}
+
+// 256 threads = 4 waves in 2 x 2; each wave owns a 32 x (kTN / 2) block of
+// the 64 x kTN tile as 2 x (kTN / 32) MFMA 16x16x16 blocks.  Operand layout
+// of the MFMA: lane l holds A[l % 16][4 (l / 16) .. +3] and
+// B[4 (l / 16) .. +3][l % 16]; result lane l holds C[4 (l / 16) + r][l % 16],
+// r = 0..3.
+template <int kTN, int kVA, int kVB>
 __global__ __launch_bounds__(256) void k_gemm(Gemm g) {
+    constexpr int kNB = kTN / 32;
     __shared__ __align__(16) uint16_t As[kTM][kPitch];
     __shared__ __align__(16) uint16_t Bs[kTN][kPitch];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wm = w >> 1, wn = w & 1;
     const int m0 = blockIdx.y * kTM, n0 = blockIdx.x * kTN;
-    const bool a_k = g.sak == 1, b_k = g.sbk == 1;
-    f32x4 acc[2][2];
+    f32x4 acc[2][kNB];
     for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int b = 0; b < kNB; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
     for (int k0 = 0; k0 < g.K; k0 += kTK) {
-#pragma unroll
-        for (int r = 0; r < (kTM * kTK) / 256; ++r) {
-            const int e = tid + 256 * r;
-            const int m = a_k ? e >> 5 : e & 63;
-            const int k = a_k ? e & 31 : e >> 6;
-            const int gm = m0 + m, gk = k0 + k;
-            As[m][k] = (gm < g.M && gk < g.K) ? g.A[gm * g.sam + gk * g.sak] : (uint16_t)0;
-            const int n = b_k ? e >> 5 : e & 63;
-            const int kb = b_k ? e & 31 : e >> 6;
-            const int gn = n0 + n, gkb = k0 + kb;
-            Bs[n][kb] = (gn < g.N && gkb < g.K) ? g.B[gkb * g.sbk + gn * g.sbn] : (uint16_t)0;
-        }
+        load_tile<kTM, kVA>(As, g.A, g.sam, g.sak, m0, g.M, k0, g.K, tid);
+        load_tile<kTN, kVB>(Bs, g.B, g.sbn, g.sbk, n0, g.N, k0, g.K, tid);
         __syncthreads();
 #pragma unroll
         for (int kk = 0; kk < kTK; kk += 16) {
-            s16x4 a[2], b[2];
+            s16x4 a[2], b[kNB];
             const int kq = kk + 4 * (lane >> 4);
             for (int mb = 0; mb < 2; ++mb)
                 a[mb] = *(const s16x4*)&As[wm * 32 + mb * 16 + (lane & 15)][kq];
-            for (int nb = 0; nb < 2; ++nb)
-                b[nb] = *(const s16x4*)&Bs[wn * 32 + nb * 16 + (lane & 15)][kq];
+            for (int nb = 0; nb < kNB; ++nb)
+                b[nb] = *(const s16x4*)&Bs[wn * (kTN / 2) + nb * 16 + (lane & 15)][kq];
             for (int mb = 0; mb < 2; ++mb)
-                for (int nb = 0; nb < 2; ++nb)
+                for (int nb = 0; nb < kNB; ++nb)
                     acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[mb], b[nb],
                                                                             acc[mb][nb], 0, 0, 0);
         }
         __syncthreads();
     }
     for (int mb = 0; mb < 2; ++mb)
-        for (int nb = 0; nb < 2; ++nb)
+        for (int nb = 0; nb < kNB; ++nb)
             for (int r = 0; r < 4; ++r) {
                 const int m = m0 + wm * 32 + mb * 16 + 4 * (lane >> 4) + r;
-                const int n = n0 + wn * 32 + nb * 16 + (lane & 15);
+                const int n = n0 + wn * (kTN / 2) + nb * 16 + (lane & 15);
                 if (m >= g.M || n >= g.N) continue;
                 float v = acc[mb][nb][r];
                 if (g.bias) v += g.bias[n];
@@ -166,8 +212,22 @@ __global__ __launch_bounds__(256) void k_gemm(Gemm g) {
 
 void gemm(const Gemm& g, hipStream_t s) {
     if (g.M <= 0 || g.N <= 0) return;
-    dim3 grid((g.N + kTN - 1) / kTN, (g.M + kTM - 1) / kTM);
-    hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, s, g);
+    // 64 x 64 tiles: the weight-gradient products (M, N <= 256, K = batch)
+    // need every workgroup they can get; a 128-wide tile measured no faster
+    // on the forward products either
+    // one instantiation per pair of operand vector widths, so that each
+    // kernel holds only its own load path (registers, occupancy)
+    const int va = vec_width(g.A, g.sam, g.sak, g.K), vb = vec_width(g.B, g.sbn, g.sbk, g.K);
+    dim3 grid((g.N + 63) / 64, (g.M + kTM - 1) / kTM);
+#define TPX_GEMM(A_, B_)                                                      \
+    if (va == A_ && vb == B_) {                                               \
+        hipLaunchKernelGGL((k_gemm<64, A_, B_>), grid, dim3(256), 0, s, g); \
+        return;                                                               \
+    }
+    TPX_GEMM(1, 1) TPX_GEMM(1, 2) TPX_GEMM(1, 4)
+    TPX_GEMM(2, 1) TPX_GEMM(2, 2) TPX_GEMM(2, 4)
+    TPX_GEMM(4, 1) TPX_GEMM(4, 2) TPX_GEMM(4, 4)
+#undef TPX_GEMM
 }
 
 // ------------------------------------------------------- loss, sums, update
