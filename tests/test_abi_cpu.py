@@ -64,3 +64,38 @@ def test_argument_errors_need_no_gpu():
     assert lib.tpx_stream_create(ctypes.byref(p), 1000, ctypes.byref(h)) == tpx.EINVAL
     p = tpx.make_params()
     assert lib.tpx_stream_create(ctypes.byref(p), 0, ctypes.byref(h)) == tpx.EINVAL
+
+
+def test_learned_and_tuning_argument_errors_need_no_gpu():
+    """Calls that return before any GPU work: empty inputs, bad sizes, NULLs."""
+    lib = tpx.load()
+    fake = ctypes.c_void_p(0x1000)          # never dereferenced on these paths
+    big = 1 << 40
+    assert lib.tpx_mlp_workspace_bytes(0) > 0
+    assert lib.tpx_mlp_workspace_bytes(4096) > lib.tpx_mlp_workspace_bytes(1024)
+    assert lib.tpx_patch_workspace_bytes(10) == 10 * 98 * 4 + 256
+    # forward of nothing is fine; without a workspace it is an error
+    assert lib.tpx_mlp_forward(fake, fake, 0, fake, fake, big, None) == tpx.OK
+    assert lib.tpx_mlp_forward(fake, fake, 5, fake, None, 0, None) == tpx.EINVAL
+    # gradient of an empty batch, Adam step 0, NULL parameters
+    loss = ctypes.c_float()
+    assert lib.tpx_mlp_grad(fake, fake, fake, fake, fake, 0, fake, ctypes.byref(loss), fake, big,
+                            None) == tpx.EINVAL
+    assert lib.tpx_mlp_grad(None, fake, fake, fake, fake, 4, fake, None, fake, big,
+                            None) == tpx.EINVAL
+    assert lib.tpx_mlp_adam(fake, fake, fake, fake, 10, 0, 1e-3, 0.9, 0.999, 1e-8,
+                            None) == tpx.EINVAL
+    assert lib.tpx_mlp_refine(fake, fake, 0, fake, None) == tpx.OK
+    # patches: nothing to do; events without hits; a workspace too small
+    ev = tpx.Events()
+    assert lib.tpx_patches(ev, None, 0, None, 0, None, fake, big, None) == tpx.OK
+    ev = tpx.Events(fake, fake, fake, fake, fake)
+    assert lib.tpx_patches(ev, fake, 3, fake, 0, fake, fake, big, None) == tpx.EINVAL
+    assert lib.tpx_patches(ev, fake, 3, fake, 2, fake, fake, 10, None) == tpx.EINVAL
+    # segment stride of a NULL stream and the autotuner's argument checks
+    assert lib.tpx_stream_set_segment(None, 512) == tpx.EINVAL
+    assert lib.tpx_stream_get_segment(None) == 0
+    cand = (ctypes.c_uint32 * 2)(64, 4096)
+    best = ctypes.c_uint32()
+    assert lib.tpx_stream_autotune(None, fake, 0, 1, fake, 0, cand, 2, 1, None,
+                                   ctypes.byref(best), None) == tpx.EINVAL

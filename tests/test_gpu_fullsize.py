@@ -71,3 +71,39 @@ def test_paper_mode_full_size_sampled(tpx, orc):
         ref["label"] = idx[ref["label"].astype(np.int64)]
         got = h[h["shot"] == s]
         assert_hits_match(got, ref)
+
+
+def test_learned_full_size_sampled(tpx):
+    """Patches and the forward pass over 10^6 generated clusters (the
+    held-out set the benchmark scores); the oracle recomputes 300 randomly
+    drawn clusters from their own events: patches bit-exact, outputs within
+    the bfloat16 tolerance of the learned-part parity tests."""
+    import torch
+
+    from oracle import learned as L
+    from paper_2603_04942_amd.learned import prepare
+    from test_gpu_learned import REL_TOL, _rand_params
+    import oracle
+    orc = oracle.get()
+    n = 1_000_000
+    cl = synth.make_clusters(4002, n, block=50_000)
+    feat, hits, _, _ = prepare(cl)
+    p = _rand_params(11)
+    out = tpx.Mlp(p, batch=16).forward(feat).cpu().numpy()
+    got = feat.cpu().numpy().view(np.uint16)
+    print(f"learned full size: {n} clusters, {cl['events']['x'].size} events", flush=True)
+    picks = np.sort(np.random.default_rng(77).choice(n, 300, replace=False))
+    e = cl["events"]
+    ref_feat = []
+    for s in picks:
+        lo, m = int(cl["first"][s]), int(cl["counts"][s])
+        sl = slice(lo, lo + m)
+        h = orc.centroid(e["x"][sl], e["y"][sl], e["tot"][sl], e["shot"][sl], e["toa"][sl],
+                         cl["labels"][sl], np.zeros(n, np.uint64))
+        ref_feat.append(L.patches(e["x"][sl], e["y"][sl], e["tot"][sl], e["toa"][sl],
+                                  e["shot"][sl], cl["labels"][sl], h)[0])
+    ref_feat = np.array(ref_feat)
+    assert np.array_equal(got[picks], ref_feat)
+    ref, _ = L.forward(p, ref_feat)
+    rms = float(np.sqrt(np.mean(ref ** 2)))
+    assert np.abs(out[picks] - ref).max() <= REL_TOL * rms
