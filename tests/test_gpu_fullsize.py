@@ -98,10 +98,11 @@ def test_learned_full_size_sampled(tpx):
     for s in picks:
         lo, m = int(cl["first"][s]), int(cl["counts"][s])
         sl = slice(lo, lo + m)
+        lab = (cl["labels"][sl] - lo).astype(np.uint32)     # indices into the slice
         h = orc.centroid(e["x"][sl], e["y"][sl], e["tot"][sl], e["shot"][sl], e["toa"][sl],
-                         cl["labels"][sl], np.zeros(n, np.uint64))
+                         lab, np.zeros(n, np.uint64))
         ref_feat.append(L.patches(e["x"][sl], e["y"][sl], e["tot"][sl], e["toa"][sl],
-                                  e["shot"][sl], cl["labels"][sl], h)[0])
+                                  e["shot"][sl], lab, h)[0])
     ref_feat = np.array(ref_feat)
     assert np.array_equal(got[picks], ref_feat)
     ref, _ = L.forward(p, ref_feat)
