@@ -324,6 +324,18 @@ void tpx_service_destroy(tpx_service* sv);
 size_t tpx_patch_workspace_bytes(size_t n_hits);
 tpx_status tpx_patches(tpx_events ev, const uint32_t* labels, size_t n_ev, const tpx_hit* hits,
                        size_t n_hits, uint16_t* feat, void* ws, size_t ws_bytes, void* stream);
+/*   tpx_stream_patches  the same patches for the n_hits hits that the last
+ *                       tpx_process_stream call on s wrote (hits: that
+ *                       call's output, n_hits its count), taken from the
+ *                       stream's own copy of the call's events (valid until
+ *                       the next call, set_state or autotune on s): the
+ *                       refinement step of the streaming loop.  ws:
+ *                       tpx_stream_patch_workspace_bytes(n_hits) bytes.
+ *                       TPX_EINVAL without such a call or with another
+ *                       count.  Synchronises. */
+size_t tpx_stream_patch_workspace_bytes(size_t n_hits);
+tpx_status tpx_stream_patches(tpx_stream* s, const tpx_hit* hits, size_t n_hits, uint16_t* feat,
+                              void* ws, size_t ws_bytes, void* stream);
 size_t tpx_mlp_workspace_bytes(size_t batch);
 tpx_status tpx_mlp_forward(const float* params, const uint16_t* feat, size_t n, float* out,
                            void* ws, size_t ws_bytes, void* stream);

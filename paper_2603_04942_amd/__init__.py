@@ -72,7 +72,8 @@ EXPORTS = ("tpx_params_default", "tpx_unwrap_state_init", "tpx_workspace_bytes",
            "tpx_service_create", "tpx_service_submit", "tpx_service_run", "tpx_service_destroy",
            "tpx_patch_workspace_bytes", "tpx_patches", "tpx_mlp_workspace_bytes",
            "tpx_mlp_forward", "tpx_mlp_grad", "tpx_mlp_adam", "tpx_mlp_refine",
-           "tpx_stream_set_segment", "tpx_stream_get_segment", "tpx_stream_autotune")
+           "tpx_stream_set_segment", "tpx_stream_get_segment", "tpx_stream_autotune",
+           "tpx_stream_patch_workspace_bytes", "tpx_stream_patches")
 
 _lib = None
 
@@ -125,6 +126,10 @@ def load(path=LIB_PATH):
     lib.tpx_stream_get_segment.restype = ctypes.c_uint32
     lib.tpx_stream_autotune.argtypes = [P, P, S, ctypes.c_int, P, S, P, S, ctypes.c_int, P, P, P]
     lib.tpx_stream_autotune.restype = I
+    lib.tpx_stream_patch_workspace_bytes.argtypes = [S]
+    lib.tpx_stream_patch_workspace_bytes.restype = S
+    lib.tpx_stream_patches.argtypes = [P, P, S, P, P, S, P]
+    lib.tpx_stream_patches.restype = I
     lib.tpx_status_str.argtypes = [I]
     lib.tpx_status_str.restype = ctypes.c_char_p
     lib.tpx_last_error.argtypes = []
@@ -384,6 +389,17 @@ class Stream:
                                           ctypes.byref(best), _stream(torch))
         _check(rc, "tpx_stream_autotune")
         return int(best.value), {int(c): float(m) for c, m in zip(candidates, ms)}
+
+    def patches(self, hits, n_hits):
+        """tpx_stream_patches: bfloat16 patches (int16 tensor [n_hits, 98]) of
+        the hits (device uint8 [>= n_hits, 48]) of the last process call."""
+        torch = self.torch
+        feat = torch.empty((max(n_hits, 1), MLP_IN), dtype=torch.int16, device="cuda")
+        ws = torch.empty(self.lib.tpx_stream_patch_workspace_bytes(n_hits), dtype=torch.uint8,
+                         device="cuda")
+        _check(self.lib.tpx_stream_patches(self.h, _ptr(hits), n_hits, _ptr(feat), _ptr(ws),
+                                           ws.numel(), _stream(torch)), "tpx_stream_patches")
+        return feat[:n_hits]
 
     def get_state(self):
         n = ctypes.c_size_t()

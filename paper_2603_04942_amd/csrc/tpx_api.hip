@@ -530,6 +530,11 @@ struct tpx_stream {
     uint64_t carry_last1;   // window index of the last carried event + 1 (0 = none)
     int cur;
     uint32_t q;             // segment stride of the clustering (events)
+    // the last successful call's clustering (its events, ranks and segment
+    // offsets stay in place until the next call): patches of its hits
+    ClusterArgs last_c;
+    uint64_t last_grid, last_hits;
+    int last_ok;
     uint64_t n_fallback;    // chunks that needed the general (sorting) path
     // optional per-stage timing with HIP events on the caller's stream
     int timing;
@@ -658,6 +663,8 @@ tpx_status stream_fast(tpx_stream* s, const uint64_t* chunk, uint64_t n, int flu
     launch_seg_table(c.grp_off, c.n_grp_dev, c.n_ev_dev, c.skip, s->q, rows, s->seg_lo, s->res, hs);
     mark(s, 4, hs);
     const uint64_t grid = cluster_grid(s->n_carry + n, s->q);
+    s->last_c = c;
+    s->last_grid = grid;
     launch_cluster(c, false, grid, hs);
     mark(s, 5, hs);
     launch_scan_u32(s->seg_cnt, s->seg_off, 0, &s->res->n_seg, s->block_tmp, hs);
@@ -708,6 +715,8 @@ tpx_status stream_general(tpx_stream* s, const uint64_t* chunk, uint64_t n, int 
     c.seg_lo = s->seg_lo;
     launch_seg_table(c.grp_off, c.n_grp_dev, c.n_ev_dev, nullptr, s->q, N, s->seg_lo, s->res, hs);
     const uint64_t grid = cluster_grid(N, s->q);
+    s->last_c = c;
+    s->last_grid = grid;
     launch_cluster(c, false, grid, hs);
     launch_scan_u32(s->seg_cnt, s->seg_off, 0, &s->res->n_seg, s->block_tmp, hs);
     launch_seg_centroid(c, grid, hs);
@@ -805,6 +814,7 @@ tpx_status tpx_process_stream(tpx_stream* s, const uint64_t* chunk, size_t n_pkt
     if (hit_cap && !hits) return fail(TPX_EINVAL, "hits is NULL");
     if (s->n_win + n_pkts + 2 > s->tab_cap) return fail(TPX_EINTERNAL, "trigger window overflow");
     hipStream_t hs = (hipStream_t)stream;
+    s->last_ok = 0;
     tpx_status rc = stream_fast(s, chunk, n_pkts, flush, hits, hit_cap, hs);
     if (rc) return rc;
     DevResults r = *s->res_h;
@@ -851,6 +861,8 @@ tpx_status tpx_process_stream(tpx_stream* s, const uint64_t* chunk, size_t n_pkt
     s->carry_rebase = (uint32_t)ws;
     s->carry_last1 = s->n_carry ? (r.carry_last - ws) : 0;
     s->cur = nx;
+    s->last_hits = r.n_hits;
+    s->last_ok = 1;
     fill_stats(stats_h, r, n_pkts, r.n_kept, r.n_hits);
     return TPX_OK;
 }
@@ -912,6 +924,7 @@ tpx_status tpx_stream_get_state(const tpx_stream* s, void* buf_h, size_t* bytes_
 }
 
 tpx_status tpx_stream_set_state(tpx_stream* s, const void* buf_h, size_t bytes) {
+    if (s) s->last_ok = 0;
     if (!s || !buf_h) return fail(TPX_EINVAL, "NULL argument");
     if (bytes < sizeof(StreamCkpt)) return fail(TPX_EINVAL, "state buffer too short");
     StreamCkpt h;
@@ -988,6 +1001,29 @@ tpx_status tpx_stream_set_segment(tpx_stream* s, uint32_t q) {
 }
 
 uint32_t tpx_stream_get_segment(const tpx_stream* s) { return s ? s->q : 0; }
+
+size_t tpx_stream_patch_workspace_bytes(size_t n_hits) { return n_hits * 99 * 4 + 256; }
+
+tpx_status tpx_stream_patches(tpx_stream* s, const tpx_hit* hits, size_t n_hits, uint16_t* feat,
+                              void* ws, size_t ws_bytes, void* stream) {
+    if (!s) return fail(TPX_EINVAL, "stream is NULL");
+    if (!s->last_ok) return fail(TPX_EINVAL, "no completed tpx_process_stream call to take hits from");
+    if (n_hits != s->last_hits)
+        return fail(TPX_EINVAL, "n_hits (%zu) is not the last call's hit count (%llu)", n_hits,
+                    (unsigned long long)s->last_hits);
+    if (n_hits && (!hits || !feat)) return fail(TPX_EINVAL, "hits or feat is NULL");
+    if (!ws || ws_bytes < tpx_stream_patch_workspace_bytes(n_hits))
+        return fail(TPX_EINVAL, "workspace too small");
+    if (n_hits == 0) return TPX_OK;
+    hipStream_t hs = (hipStream_t)stream;
+    int* err = (int*)((char*)ws + n_hits * 99 * 4);
+    launch_stream_patches(s->last_c, s->last_grid, hits, n_hits, (uint32_t*)ws, feat, err, hs);
+    int e = 0;
+    HIPCHK(hipMemcpyAsync(&e, err, 4, hipMemcpyDeviceToHost, hs));
+    HIPCHK(hipStreamSynchronize(hs));
+    if (e) return fail(TPX_EINTERNAL, "an event's component has no hit of the last call");
+    return TPX_OK;
+}
 
 // Times the chunk at every candidate stride (best of `reps`, HIP events on
 // the call's stream), restoring the stream state before every run; keeps the

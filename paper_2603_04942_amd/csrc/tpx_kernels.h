@@ -81,6 +81,11 @@ void launch_seg_table(const uint32_t* grp_off, const unsigned long long* n_grp_d
                       hipStream_t s);
 // stream mode: moments and hits of the components found by launch_cluster
 void launch_seg_centroid(const ClusterArgs& a, uint64_t grid, hipStream_t s);
+// patches of the hits written by the stream call whose cluster arguments are
+// `a` (tpx_learn.hip); acc: u32 [n_hits * 98 + n_hits] scratch, err: 1 word
+void launch_stream_patches(const ClusterArgs& a, uint64_t grid, const tpx_hit* hits,
+                           uint64_t n_hits, uint32_t* acc, uint16_t* feat, int* err,
+                           hipStream_t s);
 // event mode, the paper's local-maximum hits: count pass (write = false,
 // fills seg_cnt), then write pass (hits at seg_off[k] + rank)
 void launch_paper(const ClusterArgs& a, const uint64_t* trig, bool write, uint64_t grid,

@@ -87,6 +87,63 @@ __global__ void k_patch_finish(const uint32_t* acc, uint64_t n_hits, uint16_t* f
     feat[h * kIn + kCells + c] = d == 0xFFFFFFFFu ? (uint16_t)0 : to_bf16((float)d * (1.0f / 64.0f));
 }
 
+// Patches of the hits of a stream call, from its packed events (ToF ticks |
+// ToT << 30 | y << 40 | x << 48), component ranks and segment offsets: the
+// hit of an event is seg_off[segment] + rank.  Cells keep the smallest ToF;
+// the hit's own smallest ToF (all its events, in the window or not) is the
+// ToF of its toa_first, so cell - hit minimum = ToA - toa_first exactly.
+__global__ void k_spatch_clear(uint32_t* acc, uint64_t n_hits) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_hits * (kIn + 1)) return;
+    acc[i] = (i < n_hits * kIn && (i % kIn) < kCells) ? 0u : 0xFFFFFFFFu;
+}
+
+__global__ __launch_bounds__(256) void k_spatch_accum(ClusterArgs a, const tpx_hit* hits,
+                                                      uint64_t n_hits, uint32_t* acc, int* err) {
+    const uint64_t N = (a.skip && *a.skip) ? 0 : *a.n_ev_dev;
+    const uint64_t n_seg = (N + a.q - 1) / a.q;
+    const uint32_t k = blockIdx.x;
+    if (k >= n_seg) return;
+    const uint32_t g_lo = a.seg_lo[k], g_hi = a.seg_lo[k + 1];
+    const uint64_t e0 = a.grp_off[g_lo], e1 = a.grp_off[g_hi];
+    if (g_hi < g_lo || e1 < e0 || e1 > N) {
+        if (threadIdx.x == 0) atomicOr(err, 1);
+        return;
+    }
+    const uint32_t cnt = a.seg_cnt[k];
+    const uint64_t out0 = a.seg_off[k];
+    uint32_t* hmin = acc + n_hits * kIn;
+    for (uint64_t p = e0 + threadIdx.x; p < e1; p += blockDim.x) {
+        const uint32_t rk = a.rank[p];
+        const uint64_t h = out0 + rk;
+        if (rk >= cnt || h >= n_hits) {
+            atomicOr(err, 1);
+            continue;
+        }
+        const uint64_t pk = a.ev[p];
+        const uint32_t tof = (uint32_t)(pk & 0x3FFFFFFFu);
+        atomicMin(&hmin[h], tof);
+        const int ix = (int)((pk >> 48) & 255u) - centre_of(hits[h].x) + kHalf;
+        const int iy = (int)((pk >> 40) & 255u) - centre_of(hits[h].y) + kHalf;
+        if (ix < 0 || ix >= kSide || iy < 0 || iy >= kSide) continue;
+        const int c = iy * kSide + ix;
+        atomicAdd(&acc[h * kIn + c], (uint32_t)((pk >> 30) & 1023u));
+        atomicMin(&acc[h * kIn + kCells + c], tof);
+    }
+}
+
+__global__ void k_spatch_finish(const uint32_t* acc, uint64_t n_hits, uint16_t* feat) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_hits * kCells) return;
+    const uint64_t h = i / kCells, c = i % kCells;
+    const uint32_t s = acc[h * kIn + c];
+    const uint32_t d = acc[h * kIn + kCells + c];
+    const uint32_t m = acc[n_hits * kIn + h];
+    feat[h * kIn + c] = to_bf16((float)(s < 1023u ? s : 1023u) * (1.0f / 1024.0f));
+    feat[h * kIn + kCells + c] =
+        d == 0xFFFFFFFFu ? (uint16_t)0 : to_bf16((float)(d - m) * (1.0f / 64.0f));
+}
+
 // --------------------------------------------------------------------- GEMM
 struct Gemm {
     const uint16_t* A;
@@ -395,6 +452,20 @@ void forward(const float* params, const uint16_t* wq, const uint16_t* feat, int 
 }
 
 }  // namespace
+
+void launch_stream_patches(const ClusterArgs& a, uint64_t grid, const tpx_hit* hits,
+                           uint64_t n_hits, uint32_t* acc, uint16_t* feat, int* err,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_f32, dim3(1), dim3(64), 0, s, (float*)err, 1);
+    hipLaunchKernelGGL(k_spatch_clear, dim3(blocks(n_hits * (kIn + 1), 256)), dim3(256), 0, s,
+                       acc, n_hits);
+    if (grid)
+        hipLaunchKernelGGL(k_spatch_accum, dim3((unsigned)grid), dim3(256), 0, s, a, hits, n_hits,
+                           acc, err);
+    hipLaunchKernelGGL(k_spatch_finish, dim3(blocks(n_hits * kCells, 256)), dim3(256), 0, s, acc,
+                       n_hits, feat);
+}
+
 }  // namespace tpx
 
 using namespace tpx;

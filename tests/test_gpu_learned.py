@@ -224,3 +224,37 @@ def test_training_beats_weighted_centroid(tpx):
     assert s["single_t_rmse_ns"]["learned"] <= 0.8 * s["single_t_rmse_ns"]["centroid"]
     # single hits keep the centroid's position unless judged a pair
     assert s["single_pos_rmse_px"]["learned"] <= 1.05 * s["single_pos_rmse_px"]["centroid"]
+
+
+def test_stream_patches_match_the_oracle(tpx, orc):
+    """Patches of the hits of stream calls (one flushed chunk, then a chunked
+    replay with shots across chunk boundaries) equal the oracle's patches of
+    the whole stream's clusters, bit for bit."""
+    import torch
+    for name, shots, step in (("c1", 200, None), ("c5", 60, 15_000)):
+        w = synth.make_config(name, n_shots=shots)
+        kw = dict(pix_epoch0=w.pix_epoch0, tdc_epoch0=w.tdc_epoch0)
+        d = orc.decode(w.packets, **kw)
+        e = d["events"]
+        lab, _ = orc.cluster(e["x"], e["y"], e["shot"], e["toa"])
+        hits = orc.centroid(e["x"], e["y"], e["tot"], e["shot"], e["toa"], lab, d["trig"])
+        ref = L.patches(e["x"], e["y"], e["tot"], e["toa"], e["shot"], lab, hits)
+        step = step or w.n_packets
+        s = tpx.Stream(step, **kw)
+        buf = torch.empty((2 * step + 1024, 48), dtype=torch.uint8, device="cuda")
+        got = []
+        try:
+            with pytest.raises(tpx.TpxError) as err:
+                s.patches(buf, 0)                        # no call yet
+            assert err.value.rc == tpx.EINVAL
+            for a in range(0, w.n_packets, step):
+                h, _ = s.process(w.packets[a:a + step], flush=a + step >= w.n_packets, hits=buf)
+                got.append(s.patches(buf, h.size).cpu().numpy().view(np.uint16))
+                if h.size:
+                    with pytest.raises(tpx.TpxError):
+                        s.patches(buf, h.size + 1)       # not the last call's count
+        finally:
+            s.close()
+        got = np.concatenate(got)
+        _say(f"stream patches {name}: {got.shape[0]} hits")
+        assert np.array_equal(got, ref)
