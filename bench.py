@@ -195,11 +195,48 @@ def run_latency(args):
             lat_p, _, _ = replay(lim, speed)
             row["paced"][f"{speed:g}x"] = dict(chunks=lim, p50_ms=float(np.percentile(lat_p, 50)),
                                                p99_ms=float(np.percentile(lat_p, 99)))
+        row["refined"] = refined_replay(args, tpx, s, fresh, pk, chunk, hits, starts)
         s.close()
         del hits
         row["paced_batched"] = batched_replays(args, tpx, w, pk, chunk, pk_rate)
         out["sizes"].append(row)
     return out
+
+
+def refined_replay(args, tpx, s, fresh, pk, chunk, hits, starts):
+    """The whole streaming loop per chunk, back-to-back: decode -> cluster ->
+    centroid (tpx_process_stream), then the learned refinement of the chunk's
+    hits (tpx_stream_patches, forward, refine).  Latency does not depend on
+    the weights; an untrained network of the same shape is used."""
+    import torch
+
+    import synth
+
+    mlp = tpx.Mlp(synth.init_mlp_params(4001, zero_last=True), batch=16)
+    n_pk = pk.numel()
+
+    def one(a, last):
+        rc, nh, st = s.process_raw(pk[a:a + chunk], last, hits, chunk)
+        if rc != 0:
+            raise tpx.TpxError(rc, "tpx_process_stream", s.lib.tpx_last_error().decode())
+        if nh:
+            tpx.refine(hits[:nh], mlp.forward(s.patches(hits, nh)))
+        torch.cuda.synchronize()
+        return nh
+
+    s.set_state(fresh)
+    for i, a in enumerate(starts[:8]):
+        one(a, i == 7)
+    s.set_state(fresh)
+    lat, n_h = [], 0
+    t0 = time.perf_counter()
+    for i, a in enumerate(starts):
+        t = time.perf_counter()
+        n_h += one(a, i == len(starts) - 1)
+        lat.append((time.perf_counter() - t) * 1e3)
+    span = time.perf_counter() - t0
+    return dict(p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
+                hits_per_s=n_h / span, replay_capacity=args.latency_shots * 1e-3 / span)
 
 
 def batched_replays(args, tpx, w, pk, chunk, pk_rate):
