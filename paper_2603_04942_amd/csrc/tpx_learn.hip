@@ -16,6 +16,8 @@
 // products of the backward pass need no transposed copies; the epilogue adds
 // the bias, applies ReLU or the ReLU mask of the stored activation, and
 // writes fp32 and/or bfloat16.
+#include <type_traits>
+
 #include "tpx_kernels.h"
 
 namespace tpx {
@@ -168,45 +170,63 @@ constexpr int kTM = 64, kTK = 32, kPitch = kTK + 8;
 // thread moves `vec` consecutive k at once (a vector of 2 or 4 bfloat16);
 // otherwise one element at a time, with consecutive threads along whichever
 // of row / k is contiguous.
+// One rows x 32 tile of a strided operand, moved in two halves so that the
+// next tile's global loads are in flight while the current one is multiplied:
+// fetch() issues the loads into registers, stash() writes them to LDS as
+// [row][k].  When k is contiguous (stride 1) and K is a multiple of the
+// vector width, each thread moves `vec` consecutive k at once (a vector of 2
+// or 4 bfloat16); otherwise one element at a time, with consecutive threads
+// along whichever of row / k is contiguous.  Trip counts are compile-time
+// constants (rows * 32 / vec is a multiple of 256).
 template <int kRows, int vec>
-__device__ __forceinline__ void load_tile(uint16_t (*T)[kPitch], const uint16_t* src, int64_t s_row,
-                                          int64_t s_k, int row0, int n_rows, int k0, int K,
-                                          int tid) {
-    // trip counts are compile-time constants (kRows * 32 / vec is a multiple
-    // of 256), so every load of a tile is issued before the first wait
+struct TileRegs {
     static_assert((kRows * kTK / 4) % 256 == 0, "tile rows must be a multiple of 32");
-    if constexpr (vec == 4) {
-#pragma unroll
-        for (int it = 0; it < kRows * kTK / 4 / 256; ++it) {
-            const int e = tid + 256 * it;
-            const int r = e >> 3, k = (e & 7) * 4;
-            const int gr = row0 + r, gk = k0 + k;
-            uint2 v = make_uint2(0u, 0u);
-            if (gr < n_rows && gk < K) v = *(const uint2*)(src + gr * s_row + gk);
-            *(uint2*)&T[r][k] = v;
-        }
-    } else if constexpr (vec == 2) {
-#pragma unroll
-        for (int it = 0; it < kRows * kTK / 2 / 256; ++it) {
-            const int e = tid + 256 * it;
-            const int r = e >> 4, k = (e & 15) * 2;
-            const int gr = row0 + r, gk = k0 + k;
-            uint32_t v = 0u;
-            if (gr < n_rows && gk < K) v = *(const uint32_t*)(src + gr * s_row + gk);
-            *(uint32_t*)&T[r][k] = v;
-        }
-    } else {
-        const bool k_contig = s_k == 1;
-#pragma unroll
-        for (int it = 0; it < kRows * kTK / 256; ++it) {
-            const int e = tid + 256 * it;
-            const int r = k_contig ? e >> 5 : e % kRows;
-            const int k = k_contig ? e & 31 : e / kRows;
-            const int gr = row0 + r, gk = k0 + k;
-            T[r][k] = (gr < n_rows && gk < K) ? src[gr * s_row + gk * s_k] : (uint16_t)0;
+    static constexpr int kN = kRows * kTK / vec / 256;
+    using V = typename std::conditional<vec == 4, uint2,
+                                        typename std::conditional<vec == 2, uint32_t,
+                                                                  uint16_t>::type>::type;
+    V v[kN];
+
+    __device__ __forceinline__ static void pos(int e, bool k_contig, int* r, int* k) {
+        if constexpr (vec == 4) {
+            *r = e >> 3, *k = (e & 7) * 4;
+        } else if constexpr (vec == 2) {
+            *r = e >> 4, *k = (e & 15) * 2;
+        } else {
+            *r = k_contig ? e >> 5 : e % kRows;
+            *k = k_contig ? e & 31 : e / kRows;
         }
     }
-}
+
+    __device__ __forceinline__ void fetch(const uint16_t* src, int64_t s_row, int64_t s_k,
+                                          int row0, int n_rows, int k0, int K, int tid) {
+        const bool k_contig = s_k == 1;
+#pragma unroll
+        for (int it = 0; it < kN; ++it) {
+            int r, k;
+            pos(tid + 256 * it, k_contig, &r, &k);
+            const int gr = row0 + r, gk = k0 + k;
+            const bool in = gr < n_rows && gk < K;
+            if constexpr (vec == 4) {
+                v[it] = in ? *(const uint2*)(src + gr * s_row + gk) : make_uint2(0u, 0u);
+            } else if constexpr (vec == 2) {
+                v[it] = in ? *(const uint32_t*)(src + gr * s_row + gk) : 0u;
+            } else {
+                v[it] = in ? src[gr * s_row + gk * s_k] : (uint16_t)0;
+            }
+        }
+    }
+
+    __device__ __forceinline__ void stash(uint16_t (*T)[kPitch], int64_t s_k, int tid) const {
+        const bool k_contig = s_k == 1;
+#pragma unroll
+        for (int it = 0; it < kN; ++it) {
+            int r, k;
+            pos(tid + 256 * it, k_contig, &r, &k);
+            *(V*)&T[r][k] = v[it];
+        }
+    }
+};
 
 // vector width for a k-contiguous operand: every row start and K aligned
 __host__ inline int vec_width(const uint16_t* p, int64_t s_row, int64_t s_k, int K) {
@@ -233,10 +253,18 @@ __global__ __launch_bounds__(256) void k_gemm(Gemm g) {
     f32x4 acc[2][kNB];
     for (int a = 0; a < 2; ++a)
         for (int b = 0; b < kNB; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    TileRegs<kTM, kVA> ra;
+    TileRegs<kTN, kVB> rb;
+    ra.fetch(g.A, g.sam, g.sak, m0, g.M, 0, g.K, tid);
+    rb.fetch(g.B, g.sbn, g.sbk, n0, g.N, 0, g.K, tid);
     for (int k0 = 0; k0 < g.K; k0 += kTK) {
-        load_tile<kTM, kVA>(As, g.A, g.sam, g.sak, m0, g.M, k0, g.K, tid);
-        load_tile<kTN, kVB>(Bs, g.B, g.sbn, g.sbk, n0, g.N, k0, g.K, tid);
+        ra.stash(As, g.sak, tid);
+        rb.stash(Bs, g.sbk, tid);
         __syncthreads();
+        if (k0 + kTK < g.K) {  // the next tile's loads overlap this tile's products
+            ra.fetch(g.A, g.sam, g.sak, m0, g.M, k0 + kTK, g.K, tid);
+            rb.fetch(g.B, g.sbn, g.sbk, n0, g.N, k0 + kTK, g.K, tid);
+        }
 #pragma unroll
         for (int kk = 0; kk < kTK; kk += 16) {
             s16x4 a[2], b[kNB];
