@@ -479,6 +479,111 @@ void forward(const float* params, const uint16_t* wq, const uint16_t* feat, int 
     gemm(g, s);
 }
 
+// ------------------------------------------------------ fused forward pass
+// Inference only: one workgroup per 64 rows runs all three layers with the
+// input tile and both hidden activations in LDS (no hidden activations in
+// HBM); weights come from L2 straight into the MFMA operand registers, the
+// next k-step's prefetched.  Same products in the same order and the same
+// epilogue rounding as the layered GEMMs.
+constexpr int kFR = 64, kXK = 112, kXP = kXK + 8, kHP = kHid + 8;
+
+__device__ __forceinline__ s16x4 load_w4(const uint16_t* p, bool aligned8) {
+    if (aligned8) return *(const s16x4*)p;
+    const uint2 t = make_uint2(*(const uint32_t*)p, *(const uint32_t*)(p + 2));
+    s16x4 v;
+    __builtin_memcpy(&v, &t, 8);
+    return v;
+}
+
+// Out[64][256] = relu(A[64][K] W^T + bias) in bfloat16; wave w computes
+// columns [64 w, 64 w + 64) as 4 x 4 MFMA blocks.  W rows are `ldw` apart;
+// operand k beyond a row's end meets zeros of A (the padding of layer 1).
+template <int K, int P>
+__device__ __forceinline__ void dense_relu(const uint16_t (*A)[P], const uint16_t* W, int ldw,
+                                           const float* bias, uint16_t (*Out)[kHP], int w,
+                                           int lane) {
+    const int j = lane & 15, kq = 4 * (lane >> 4);
+    const bool al = (ldw % 4) == 0;
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    s16x4 bc[4], bn[4];
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) bc[nb] = load_w4(W + (int64_t)(w * 64 + nb * 16 + j) * ldw + kq, al);
+    for (int k0 = 0; k0 < K; k0 += 16) {
+        if (k0 + 16 < K) {
+#pragma unroll
+            for (int nb = 0; nb < 4; ++nb)
+                bn[nb] = load_w4(W + (int64_t)(w * 64 + nb * 16 + j) * ldw + k0 + 16 + kq, al);
+        }
+        s16x4 a[4];
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb) a[mb] = *(const s16x4*)&A[mb * 16 + j][k0 + kq];
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < 4; ++nb)
+                acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[mb], bc[nb], acc[mb][nb],
+                                                                        0, 0, 0);
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) bc[nb] = bn[nb];
+    }
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = mb * 16 + 4 * (lane >> 4) + r, col = w * 64 + nb * 16 + j;
+                float v = acc[mb][nb][r] + bias[col];
+                Out[row][col] = to_bf16(v > 0.f ? v : 0.f);
+            }
+}
+
+__global__ __launch_bounds__(256, 2) void k_mlp_fused(const float* __restrict__ params,
+                                                      const uint16_t* __restrict__ wq,
+                                                      const uint16_t* __restrict__ feat, int n,
+                                                      float* __restrict__ out) {
+    __shared__ __align__(16) uint16_t H1[kFR][kHP];
+    __shared__ __align__(16) uint16_t XB[kFR * kHP];  // X [64][kXP] in layer 1, then H2 [64][kHP]
+    uint16_t(*X)[kXP] = (uint16_t(*)[kXP])XB;
+    uint16_t(*H2)[kHP] = (uint16_t(*)[kHP])XB;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int r0 = blockIdx.x * kFR;
+    // input tile, zero beyond the 98 features and the last row
+    for (int e = tid; e < kFR * (kXK / 2); e += 256) {
+        const int r = e / (kXK / 2), c = 2 * (e % (kXK / 2));
+        uint32_t v = 0u;
+        if (r0 + r < n && c < kIn) v = *(const uint32_t*)(feat + (int64_t)(r0 + r) * kIn + c);
+        *(uint32_t*)&X[r][c] = v;
+    }
+    __syncthreads();
+    dense_relu<kXK, kXP>(X, wq + kOffW1, kIn, params + kOffB1, H1, w, lane);
+    __syncthreads();
+    dense_relu<kHid, kHP>(H1, wq + kOffW2, kHid, params + kOffB2, H2, w, lane);
+    __syncthreads();
+    // output layer: wave w takes rows [16 w, 16 w + 16), columns 0..7 of a
+    // 16-wide MFMA block
+    const int j = lane & 15, kq = 4 * (lane >> 4);
+    f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < kHid; k0 += 16) {
+        const s16x4 a = *(const s16x4*)&H2[w * 16 + j][k0 + kq];
+        s16x4 b = s16x4{0, 0, 0, 0};
+        if (j < kOut) b = *(const s16x4*)(wq + kOffW3 + j * kHid + k0 + kq);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+    }
+    if (j < kOut) {
+        const float b3 = params[kOffB3 + j];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = r0 + w * 16 + 4 * (lane >> 4) + r;
+            if (row < n) out[(int64_t)row * kOut + j] = acc[r] + b3;
+        }
+    }
+}
+
 }  // namespace
 
 void launch_stream_patches(const ClusterArgs& a, uint64_t grid, const tpx_hit* hits,
@@ -544,7 +649,8 @@ tpx_status tpx_mlp_forward(const float* params, const uint16_t* feat, size_t n, 
                        (uint64_t)kNParam, w.wq);
     for (size_t r0 = 0; r0 < n; r0 += rows) {
         const int m = (int)(n - r0 < rows ? n - r0 : rows);
-        forward(params, w.wq, feat + r0 * kIn, m, w.h1, w.h2, out + r0 * kOut, s);
+        hipLaunchKernelGGL(k_mlp_fused, dim3(blocks((uint64_t)m, kFR)), dim3(256), 0, s, params,
+                           w.wq, feat + r0 * kIn, m, out + r0 * kOut);
     }
     if (hipGetLastError() != hipSuccess) return report(TPX_EHIP, "forward launch failed");
     return TPX_OK;
