@@ -598,6 +598,9 @@ def main():
         # (about 10 particles per shot at 1 kHz, batched on a desktop GPU)
         "paper_acquisition_multiple": 25,
     }
+    if not args.no_latency:
+        out["stream_latency"] = run_latency(args)
+        log(f"latency: {out['stream_latency']}")
     if not args.no_uneven:
         out["uneven"] = run_uneven(args, wl3)
         del wl3
@@ -605,9 +608,6 @@ def main():
     if not args.no_paper_mode:
         out["paper_mode"] = run_paper_mode(args, wl)
         log(f"paper mode: {out['paper_mode']}")
-    if not args.no_latency:
-        out["stream_latency"] = run_latency(args)
-        log(f"latency: {out['stream_latency']}")
     if pool is not None:
         out["learned"] = run_learned(args, pool, out["hits_per_s"])
         pool.terminate()
