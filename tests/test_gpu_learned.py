@@ -258,3 +258,31 @@ def test_stream_patches_match_the_oracle(tpx, orc):
         got = np.concatenate(got)
         _say(f"stream patches {name}: {got.shape[0]} hits")
         assert np.array_equal(got, ref)
+
+
+def test_stream_patches_after_the_sorting_path(tpx, orc):
+    """A kept pixel reported after pixels of a later shot sends the chunk
+    through the general (sorting) path; patches of its hits still equal the
+    oracle's."""
+    import torch
+    w = synth.make_config("c1", n_shots=60)
+    pk = w.packets.copy()
+    kept = np.nonzero(w.kept_mask())[0]
+    i = kept[np.argmax(w.shot[kept] == 10)]
+    j = kept[np.argmax(w.shot[kept] == 12)]
+    moved = np.concatenate([pk[:i], pk[i + 1:j + 1], pk[i:i + 1], pk[j + 1:]])
+    kw = dict(pix_epoch0=w.pix_epoch0, tdc_epoch0=w.tdc_epoch0)
+    d = orc.decode(moved, **kw)
+    e = d["events"]
+    lab, _ = orc.cluster(e["x"], e["y"], e["shot"], e["toa"])
+    hits = orc.centroid(e["x"], e["y"], e["tot"], e["shot"], e["toa"], lab, d["trig"])
+    ref = L.patches(e["x"], e["y"], e["tot"], e["toa"], e["shot"], lab, hits)
+    s = tpx.Stream(moved.size, **kw)
+    buf = torch.empty((moved.size, 48), dtype=torch.uint8, device="cuda")
+    try:
+        h, _ = s.process(moved, flush=True, hits=buf)
+        assert s.fallback_count == 1
+        got = s.patches(buf, h.size).cpu().numpy().view(np.uint16)
+    finally:
+        s.close()
+    assert np.array_equal(got, ref)
