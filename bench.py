@@ -584,6 +584,8 @@ def main():
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
             "algorithmic_bytes": sb[dom],
+            # measured HBM bytes per launch over the same launch time
+            "traffic_gbs": None if traffic is None else traffic / (stages[dom] * 1e-3) / 1e9,
         },
         "path_roofline": {
             "algorithmic_bytes_per_step": int(path_bytes),
