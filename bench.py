@@ -493,6 +493,40 @@ def run_cpu_baseline(wl, frac):
                        f"events, single-threaded C oracle, {dt:.1f} s")
 
 
+def _oracle_job(job):
+    import oracle
+    pk, kw = job
+    t = time.perf_counter()
+    _, st = oracle.get().run(pk, **kw)
+    return st["n_events"], time.perf_counter() - t
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def run_cpu_multicore(pool, wl, procs):
+    """The oracle in `procs` concurrent processes (the worker pool forked
+    before the GPU was touched), each on the leading 1/16 of the c2 packets:
+    events of all processes over the slowest one's time."""
+    n = wl.n_packets // 16
+    pk = np.ascontiguousarray(wl.packets[:n])
+    kw = dict(pix_epoch0=wl.pix_epoch0, tdc_epoch0=wl.tdc_epoch0)
+    res = pool.map(_oracle_job, [(pk, kw)] * procs, chunksize=1)
+    ev = sum(r[0] for r in res)
+    t_max = max(r[1] for r in res)
+    return dict(value=ev / t_max, unit="events/s", processes=procs, cpu_model=_cpu_model(),
+                sample=f"first {n} packets of the c2 stream in each of {procs} processes, "
+                       f"slowest {t_max:.1f} s")
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -612,13 +646,19 @@ def main():
         log(f"paper mode: {out['paper_mode']}")
     if pool is not None:
         out["learned"] = run_learned(args, pool, out["hits_per_s"])
-        pool.terminate()
         log(f"learned: {out['learned']}")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = run_cpu_baseline(wl, args.cpu_frac)
         out["cpu_baseline"]["acquisition_multiple"] = (out["cpu_baseline"]["value"]
                                                        / (n_ev / (args.shots * 1e-3)))
         log(f"cpu baseline: {out['cpu_baseline']}")
+        if pool is not None:
+            mc = run_cpu_multicore(pool, wl, args.workers)
+            mc["acquisition_multiple"] = mc["value"] / (n_ev / (args.shots * 1e-3))
+            out["cpu_baseline"]["multicore"] = mc
+            log(f"cpu multicore: {mc}")
+    if pool is not None:
+        pool.terminate()
     print(json.dumps(out), flush=True)
 
 
