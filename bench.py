@@ -199,6 +199,7 @@ def run_latency(args):
         s.close()
         del hits
         row["paced_batched"] = batched_replays(args, tpx, w, pk, chunk, pk_rate)
+        row["paced_batched_threaded"] = threaded_replays(args, tpx, w, pk, chunk, pk_rate)
         out["sizes"].append(row)
     return out
 
@@ -240,6 +241,61 @@ def refined_replay(args, tpx, s, fresh, pk, chunk, hits, starts):
 
 
 def batched_replays(args, tpx, w, pk, chunk, pk_rate):
+    """Paced replays through tpx_service from one thread: every chunk released
+    so far is admitted, then one run takes all of them (up to the batch
+    limit); when chunks arrive faster than one call per chunk can finish,
+    several go into one call.  Latency of a chunk = completion of its run -
+    its release."""
+    import ctypes
+
+    import torch
+
+    n_pk = pk.numel()
+    starts = list(range(0, n_pk, chunk))
+    max_batch = max(1 << 19, 4 * chunk)
+    cap = 2 * max_batch
+    hits = torch.empty((cap, 48), dtype=torch.uint8, device="cuda")
+    res = {"max_batch_packets": max_batch}
+    for speed in args.latency_speeds:
+        lim = max(1, min(len(starts), int(2.0 * pk_rate * speed / chunk)))
+        sv = tpx.Service(max_batch, pix_epoch0=w.pix_epoch0, tdc_epoch0=w.tdc_epoch0)
+        ptrs = [ctypes.c_void_p(pk[a:a + chunk].data_ptr()) for a in starts[:lim]]
+        sizes = [min(chunk, n_pk - a) for a in starts[:lim]]
+        hstream = tpx._stream(torch)
+        submit = sv.lib.tpx_service_submit
+        t0 = time.perf_counter()
+        rel = [t0 + min(a + chunk, n_pk) / pk_rate / speed for a in starts[:lim]]
+        nxt = done = runs = 0
+        pending, lat = [], []
+        while done < lim:
+            if nxt < lim and not pending:
+                while time.perf_counter() < rel[nxt]:
+                    pass
+            while nxt < lim and time.perf_counter() >= rel[nxt]:
+                rc = submit(sv.h, ptrs[nxt], sizes[nxt], 1, None, hstream)
+                if rc == tpx.ECAPACITY:
+                    break
+                if rc != 0:
+                    raise tpx.TpxError(rc, "tpx_service_submit", sv.lib.tpx_last_error().decode())
+                pending.append(rel[nxt])
+                nxt += 1
+            rc, nh, nd, st = sv.run_raw(nxt == lim, hits, cap)
+            t = time.perf_counter()
+            if rc != 0:
+                raise tpx.TpxError(rc, "tpx_service_run", sv.lib.tpx_last_error().decode())
+            k = nd - done
+            lat += [(t - r) * 1e3 for r in pending[:k]]
+            pending = pending[k:]
+            done = nd
+            runs += 1
+        sv.close()
+        res[f"{speed:g}x"] = dict(chunks=lim, runs=runs, p50_ms=float(np.percentile(lat, 50)),
+                                  p99_ms=float(np.percentile(lat, 99)))
+    del hits
+    return res
+
+
+def threaded_replays(args, tpx, w, pk, chunk, pk_rate):
     """Paced replays through tpx_service: a producer thread admits chunk k when
     it is released (its copy goes on the service's own stream and overlaps
     the batch in flight); the main thread runs the service in a loop, each run
