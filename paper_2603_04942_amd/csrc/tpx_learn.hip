@@ -161,6 +161,8 @@ struct Gemm {
     int64_t ldc32;
     uint16_t* C16;          // or null
     int64_t ldc16;
+    int k_chunk;            // k per workgroup along z (split-K); K when not split
+    int64_t split_stride;   // C32 offset between the z slices
 };
 
 constexpr int kTM = 64, kTK = 32, kPitch = kTK + 8;
@@ -255,15 +257,18 @@ __global__ __launch_bounds__(256) void k_gemm(Gemm g) {
         for (int b = 0; b < kNB; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
     TileRegs<kTM, kVA> ra;
     TileRegs<kTN, kVB> rb;
-    ra.fetch(g.A, g.sam, g.sak, m0, g.M, 0, g.K, tid);
-    rb.fetch(g.B, g.sbn, g.sbk, n0, g.N, 0, g.K, tid);
-    for (int k0 = 0; k0 < g.K; k0 += kTK) {
+    // this workgroup's range of k (all of it unless split along z)
+    const int kb = (int)blockIdx.z * g.k_chunk;
+    const int ke = g.K < kb + g.k_chunk ? g.K : kb + g.k_chunk;
+    ra.fetch(g.A, g.sam, g.sak, m0, g.M, kb, ke, tid);
+    rb.fetch(g.B, g.sbn, g.sbk, n0, g.N, kb, ke, tid);
+    for (int k0 = kb; k0 < ke; k0 += kTK) {
         ra.stash(As, g.sak, tid);
         rb.stash(Bs, g.sbk, tid);
         __syncthreads();
-        if (k0 + kTK < g.K) {  // the next tile's loads overlap this tile's products
-            ra.fetch(g.A, g.sam, g.sak, m0, g.M, k0 + kTK, g.K, tid);
-            rb.fetch(g.B, g.sbn, g.sbk, n0, g.N, k0 + kTK, g.K, tid);
+        if (k0 + kTK < ke) {  // the next tile's loads overlap this tile's products
+            ra.fetch(g.A, g.sam, g.sak, m0, g.M, k0 + kTK, ke, tid);
+            rb.fetch(g.B, g.sbn, g.sbk, n0, g.N, k0 + kTK, ke, tid);
         }
 #pragma unroll
         for (int kk = 0; kk < kTK; kk += 16) {
@@ -290,20 +295,33 @@ __global__ __launch_bounds__(256) void k_gemm(Gemm g) {
                 if (g.bias) v += g.bias[n];
                 if (g.relu) v = v > 0.f ? v : 0.f;
                 if (g.mask && !(from_bf16(g.mask[m * g.ldmask + n]) > 0.f)) v = 0.f;
-                if (g.C32) g.C32[m * g.ldc32 + n] = v;
+                if (g.C32) g.C32[blockIdx.z * g.split_stride + m * g.ldc32 + n] = v;
                 if (g.C16) g.C16[m * g.ldc16 + n] = to_bf16(v);
             }
 }
 
-void gemm(const Gemm& g, hipStream_t s) {
+// k per slice when k is split `splits` ways (a multiple of the tile depth),
+// and the number of slices that then cover K
+inline int split_chunk(int K, int splits) {
+    const int c = (((K + splits - 1) / splits + kTK - 1) / kTK) * kTK;
+    return c < kTK ? kTK : c;
+}
+inline int split_count(int K, int chunk) {
+    const int n = (K + chunk - 1) / chunk;
+    return n < 1 ? 1 : n;
+}
+
+void gemm(Gemm g, hipStream_t s, int splits = 1) {
     if (g.M <= 0 || g.N <= 0) return;
+    g.k_chunk = split_chunk(g.K, splits);
+    splits = split_count(g.K, g.k_chunk);
     // 64 x 64 tiles: the weight-gradient products (M, N <= 256, K = batch)
     // need every workgroup they can get; a 128-wide tile measured no faster
     // on the forward products either
     // one instantiation per pair of operand vector widths, so that each
     // kernel holds only its own load path (registers, occupancy)
     const int va = vec_width(g.A, g.sam, g.sak, g.K), vb = vec_width(g.B, g.sbn, g.sbk, g.K);
-    dim3 grid((g.N + 63) / 64, (g.M + kTM - 1) / kTM);
+    dim3 grid((g.N + 63) / 64, (g.M + kTM - 1) / kTM, splits);
 #define TPX_GEMM(A_, B_)                                                      \
     if (va == A_ && vb == B_) {                                               \
         hipLaunchKernelGGL((k_gemm<64, A_, B_>), grid, dim3(256), 0, s, g); \
@@ -313,6 +331,36 @@ void gemm(const Gemm& g, hipStream_t s) {
     TPX_GEMM(2, 1) TPX_GEMM(2, 2) TPX_GEMM(2, 4)
     TPX_GEMM(4, 1) TPX_GEMM(4, 2) TPX_GEMM(4, 4)
 #undef TPX_GEMM
+}
+
+// sums the z slices of a split-K product in slice order (deterministic)
+__global__ void k_sum_splits(const float* part, int splits, int M, int N, float* C, int64_t ldc) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= M * N) return;
+    float v = 0.f;
+    for (int z = 0; z < splits; ++z) v += part[(int64_t)z * M * N + i];
+    C[(int64_t)(i / N) * ldc + i % N] = v;
+}
+
+constexpr int kMaxSplits = 16;
+
+// A weight-gradient product (M, N <= 256, K = batch, plain fp32 output): few
+// output tiles and a long k, so k is split over up to 16 workgroups per tile
+// into `part` (kMaxSplits * M * N floats) and the slices summed in order.
+void gemm_wgrad(const Gemm& g, float* part, hipStream_t s) {
+    const int tiles = ((g.N + 63) / 64) * ((g.M + kTM - 1) / kTM);
+    int splits = g.K / 256;
+    if (splits > kMaxSplits) splits = kMaxSplits;
+    if (tiles >= 64 || splits < 2) {
+        gemm(g, s);
+        return;
+    }
+    Gemm h = g;
+    h.C32 = part, h.ldc32 = g.N, h.split_stride = (int64_t)g.M * g.N;
+    gemm(h, s, splits);
+    const int used = split_count(g.K, split_chunk(g.K, splits));
+    hipLaunchKernelGGL(k_sum_splits, dim3((g.M * g.N + 255) / 256), dim3(256), 0, s, part, used,
+                       g.M, g.N, g.C32, g.ldc32);
 }
 
 // ------------------------------------------------------- loss, sums, update
@@ -425,13 +473,14 @@ inline unsigned blocks(uint64_t n, unsigned t) { return (unsigned)((n + t - 1) /
 // workspace of one pass over `rows` samples
 struct MlpWs {
     uint16_t *wq, *h1, *h2, *g16, *z2_16, *z1_16;
-    float *o, *g32, *z2_32, *z1_32, *loss;
+    float *o, *g32, *z2_32, *z1_32, *loss, *part;
 };
 
 size_t mlp_ws_bytes(size_t rows) {
     auto r = [](size_t b) { return (b + 255) & ~(size_t)255; };
     return r(kNParam * 2) + 2 * r(rows * kHid * 2) + r(rows * kOut * 2) + 2 * r(rows * kHid * 2) +
-           r(rows * kOut * 4) + r(rows * kOut * 4) + 2 * r(rows * kHid * 4) + r(64);
+           r(rows * kOut * 4) + r(rows * kOut * 4) + 2 * r(rows * kHid * 4) + r(64) +
+           r((size_t)kMaxSplits * kHid * kHid * 4);
 }
 
 MlpWs carve_mlp(void* ws, size_t rows) {
@@ -453,6 +502,7 @@ MlpWs carve_mlp(void* ws, size_t rows) {
     w.z2_32 = (float*)take(rows * kHid * 4);
     w.z1_32 = (float*)take(rows * kHid * 4);
     w.loss = (float*)take(64);
+    w.part = (float*)take((size_t)kMaxSplits * kHid * kHid * 4);
     return w;
 }
 
@@ -675,7 +725,7 @@ tpx_status tpx_mlp_grad(const float* params, const uint16_t* feat, const tpx_hit
     // layer 3: dW3 = G^T H2, db3 = sum G, dZ2 = (G W3) * [H2 > 0]
     Gemm g = mk(w.g16, 1, kOut, w.h2, kHid, 1, kOut, kHid, B);
     g.C32 = grad + kOffW3, g.ldc32 = kHid;
-    gemm(g, s);
+    gemm_wgrad(g, w.part, s);
     hipLaunchKernelGGL(k_colsum, dim3(kOut), dim3(256), 0, s, w.g32, B, kOut, grad + kOffB3);
     g = mk(w.g16, kOut, 1, w.wq + kOffW3, kHid, 1, B, kHid, kOut);
     g.mask = w.h2, g.ldmask = kHid, g.C32 = w.z2_32, g.ldc32 = kHid, g.C16 = w.z2_16, g.ldc16 = kHid;
@@ -683,7 +733,7 @@ tpx_status tpx_mlp_grad(const float* params, const uint16_t* feat, const tpx_hit
     // layer 2: dW2 = dZ2^T H1, db2 = sum dZ2, dZ1 = (dZ2 W2) * [H1 > 0]
     g = mk(w.z2_16, 1, kHid, w.h1, kHid, 1, kHid, kHid, B);
     g.C32 = grad + kOffW2, g.ldc32 = kHid;
-    gemm(g, s);
+    gemm_wgrad(g, w.part, s);
     hipLaunchKernelGGL(k_colsum, dim3(kHid), dim3(256), 0, s, w.z2_32, B, kHid, grad + kOffB2);
     g = mk(w.z2_16, kHid, 1, w.wq + kOffW2, kHid, 1, B, kHid, kHid);
     g.mask = w.h1, g.ldmask = kHid, g.C32 = w.z1_32, g.ldc32 = kHid, g.C16 = w.z1_16, g.ldc16 = kHid;
@@ -691,7 +741,7 @@ tpx_status tpx_mlp_grad(const float* params, const uint16_t* feat, const tpx_hit
     // layer 1: dW1 = dZ1^T X, db1 = sum dZ1
     g = mk(w.z1_16, 1, kHid, feat, kIn, 1, kHid, kIn, B);
     g.C32 = grad + kOffW1, g.ldc32 = kIn;
-    gemm(g, s);
+    gemm_wgrad(g, w.part, s);
     hipLaunchKernelGGL(k_colsum, dim3(kHid), dim3(256), 0, s, w.z1_32, B, kHid, grad + kOffB1);
     if (hipGetLastError() != hipSuccess) return report(TPX_EHIP, "gradient launch failed");
     if (loss_h) {
