@@ -4,6 +4,7 @@ import numpy as np
 import pytest
 
 import synth
+from cases import tiny_cluster_case
 
 pytestmark = pytest.mark.gpu
 
@@ -21,15 +22,8 @@ def tpx():
 # ----------------------------------------------------------------- cluster
 @pytest.mark.parametrize("seed", range(60))
 def test_cluster_tiny(tpx, orc, seed):
-    if seed == 0:
-        pytest.skip("this input hung an earlier cluster kernel on the GPU; the cause was not "
-                    "identified, so the case stays off the GPU (see DESIGN.md, open issues)")
-    rng = np.random.default_rng(1000 + seed)
-    n = int(rng.integers(1, 300))
-    ev = synth.tiny_events(rng, n, grid=int(rng.integers(2, 12)), t_span=int(rng.integers(0, 800)),
-                           n_shots=int(rng.integers(1, 5)), sort_by_shot=bool(seed % 2))
-    dxy = int(rng.integers(0, 4))
-    dt = int(rng.choice([0, 1, 64, 128, 500]))
+    print(f"cluster tiny seed {seed}", flush=True)
+    ev, dxy, dt = tiny_cluster_case(seed)
     ref, nref = orc.cluster(ev["x"], ev["y"], ev["shot"], ev["toa"], dxy=dxy, dt_ticks=dt)
     d = tpx.to_device_events(ev)
     lab, nc = tpx.cluster(d, params=tpx.make_params(dxy=dxy, dt_ticks=dt))
