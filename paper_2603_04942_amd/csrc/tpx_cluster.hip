@@ -743,9 +743,10 @@ constexpr int kHitCap = 1024;  // components per segment accumulated in LDS
 // component at seg_off[k] + rank: X = sum(ToT x) / sum(ToT), same for Y and
 // ToF; plain means when a component has no ToT at all.
 __global__ __launch_bounds__(kCWG) void k_seg_centroid(ClusterArgs a) {
-    __shared__ uint32_t W[kHitCap], SX[kHitCap], SY[kHitCap], CNT[kHitCap], TMIN[kHitCap],
-        MINP[kHitCap];
-    __shared__ unsigned long long ST[kHitCap];
+    // 64-bit weighted sums: a component of more than 2^32 / (1023 * 255)
+    // = 16,464 pixels could overflow 32 bits
+    __shared__ uint32_t CNT[kHitCap], TMIN[kHitCap], MINP[kHitCap];
+    __shared__ unsigned long long W[kHitCap], SX[kHitCap], SY[kHitCap], ST[kHitCap];
     __shared__ uint32_t goff[kCWG + 1];
     const int tid = threadIdx.x;
     const uint32_t k = blockIdx.x;
@@ -844,9 +845,9 @@ __global__ __launch_bounds__(kCWG) void k_seg_centroid(ClusterArgs a) {
             continue;
         }
         const uint32_t x = ev_x(pk), y = ev_y(pk), tot = ev_tot(pk), t = ev_t(pk);
-        atomicAdd(&W[rk], tot);
-        atomicAdd(&SX[rk], tot * x);
-        atomicAdd(&SY[rk], tot * y);
+        atomicAdd(&W[rk], (unsigned long long)tot);
+        atomicAdd(&SX[rk], (unsigned long long)(tot * x));
+        atomicAdd(&SY[rk], (unsigned long long)(tot * y));
         atomicAdd(&CNT[rk], 1u);
         atomicMin(&TMIN[rk], t);
         atomicMin(&MINP[rk], i);
@@ -862,8 +863,8 @@ __global__ __launch_bounds__(kCWG) void k_seg_centroid(ClusterArgs a) {
             const uint32_t rk = a.rank[e0 + i];
             if (rk < cnt && W[rk] == 0) {
                 const uint64_t pk = a.ev[e0 + i];
-                atomicAdd(&SX[rk], ev_x(pk));
-                atomicAdd(&SY[rk], ev_y(pk));
+                atomicAdd(&SX[rk], (unsigned long long)ev_x(pk));
+                atomicAdd(&SY[rk], (unsigned long long)ev_y(pk));
                 atomicAdd(&ST[rk], (unsigned long long)time_term1(a, ev_tot(pk), ev_t(pk)));
             }
         }

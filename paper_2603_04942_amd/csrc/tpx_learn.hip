@@ -313,6 +313,9 @@ inline int split_count(int K, int chunk) {
 
 void gemm(Gemm g, hipStream_t s, int splits = 1) {
     if (g.M <= 0 || g.N <= 0) return;
+    // split-K slices are partial sums: an epilogue (bias, ReLU, mask, the
+    // bfloat16 copy) applies only to a whole sum, so such products run unsplit
+    if (g.bias || g.relu || g.mask || g.C16) splits = 1;
     g.k_chunk = split_chunk(g.K, splits);
     splits = split_count(g.K, g.k_chunk);
     // 64 x 64 tiles: the weight-gradient products (M, N <= 256, K = batch)

@@ -130,8 +130,21 @@ def test_forward_large_batch_chunks(tpx):
     assert np.abs(out[rows] - ref).max() <= REL_TOL * rms
 
 
-@pytest.mark.parametrize("n,seed", [(2, 1), (300, 2), (700, 3)])
-def test_gradients_match_oracle(tpx, orc, n, seed):
+# Element-wise gradient bound, relative to the RMS of each tensor: each
+# element is a sum over the batch of products of bfloat16-rounded operands, so
+# its error is a random walk of 2^-9-sized relative errors of its terms; over
+# the ~25,000 elements of the largest tensor the extreme is about 4.5 standard
+# deviations of that walk.  A dropped or shifted split-K slice (1/16 of an
+# element's terms at batch 4096) moves the largest elements by ~25 % of the RMS.
+ELEM_TOL = 6e-2
+
+
+@pytest.mark.parametrize("n,n_use,seed", [(2, None, 1), (300, None, 2), (700, None, 3),
+                                          (4300, 4096, 4), (4300, 4100, 5)])
+def test_gradients_match_oracle(tpx, orc, n, n_use, seed):
+    """Gradients element by element; batches of 4,096 and 4,100 rows split the
+    weight-gradient products into 16 full slices of 256 and into 15 slices of
+    288 with a partial last one."""
     import torch
     cl = synth.make_clusters(200 + seed, n)
     hits, feat = _oracle_inputs(orc, cl)
@@ -145,6 +158,9 @@ def test_gradients_match_oracle(tpx, orc, n, seed):
     c2 = ((pa - T[:, 1]) ** 2).sum(1) + ((pb - T[:, 0]) ** 2).sum(1)
     ok = (cl["mult"] == 1) | (np.abs(c1 - c2) > 0.05 * (c1 + c2))
     idx = np.nonzero(ok)[0]
+    if n_use is not None:
+        assert len(idx) >= n_use
+        idx = idx[:n_use]
     loss_ref, g_ref, _ = L.grad(p, feat[idx], T[idx], cl["mult"][idx])
     from paper_2603_04942_amd.learned import prepare
     gfeat, ghits, gtruth, gmult = prepare(cl)
@@ -156,8 +172,11 @@ def test_gradients_match_oracle(tpx, orc, n, seed):
     assert abs(loss - loss_ref) <= REL_TOL * abs(loss_ref)
     for name, a, b in zip([s for s, _ in L.SHAPES], L.unpack(g).values(), L.unpack(g_ref).values()):
         r = _rel(a.ravel(), b.ravel())
-        _say(f"  grad {name}: rel {r:.2e}")
+        rms = float(np.sqrt(np.mean(b.ravel() ** 2)))
+        e = float(np.abs(a.ravel() - b.ravel()).max()) / max(rms, 1e-30)
+        _say(f"  grad {name}: rel {r:.2e}, max element error / rms {e:.2e}")
         assert r <= REL_TOL, name
+        assert e <= ELEM_TOL, name
 
 
 def test_adam_matches_oracle(tpx):

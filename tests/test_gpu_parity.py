@@ -163,6 +163,87 @@ def test_stream_many_components(tpx, orc, n_iso):
     assert_hits_match(h, ref)
 
 
+def test_stream_component_beyond_32bit_moments(tpx, orc):
+    """One component of 36,992 pixels (a 136 x 136 square at ToT 1023, fired
+    twice 50 ticks apart, x and y up to 255): its sum of ToT * x is about
+    7e9, beyond 32 bits, so the moments must be accumulated in 64 bits."""
+    _say("component beyond 32-bit moments")
+    trig = np.array([1_000_000, 1_000_000 + synth.SHOT_PERIOD_TICKS])
+    bx, by = np.meshgrid(np.arange(120, 256), np.arange(120, 256))
+    x = np.concatenate([bx.ravel(), bx.ravel()])
+    y = np.concatenate([by.ravel(), by.ravel()])
+    t = np.concatenate([np.full(bx.size, trig[0] + 1000), np.full(bx.size, trig[0] + 1050)])
+    tot = np.full(x.size, 1023)
+    assert int((tot * x).sum()) >= 1 << 32
+    pk = np.concatenate([synth.encode_tdc(trig[:1], [0]),
+                         synth.encode_pixels(x, y, tot, t),
+                         synth.encode_tdc(trig[1:], [1])])
+    ref, _ = orc.run(pk)
+    assert ref.size == 1 and ref["npix"][0] == x.size
+    h, _ = tpx.process_stream(pk)
+    assert_hits_match(h, ref)
+
+
+def test_streams_concurrent_on_two_hip_streams(tpx, orc):
+    """Two tpx_stream objects driven at once from two host threads, each on its
+    own HIP stream, chunk by chunk: each gives the hits it gives alone (and the
+    oracle's)."""
+    import threading
+
+    import torch
+    work = []
+    for name, shots, seed in (("c5", 120, 3), ("c1", 600, 4)):
+        w = synth.make_config(name, n_shots=shots)
+        kw = dict(pix_epoch0=w.pix_epoch0, tdc_epoch0=w.tdc_epoch0)
+        ref, _ = orc.run(w.packets, **kw)
+        rng = np.random.default_rng(seed)
+        cuts = np.sort(rng.choice(np.arange(1, w.n_packets), 12, replace=False))
+        parts = np.split(w.packets, cuts)
+        work.append((kw, ref, parts))
+    alone = []
+    for kw, ref, parts in work:
+        s = tpx.Stream(max(len(p) for p in parts), **kw)
+        h = np.concatenate([s.process(p, flush=(i == len(parts) - 1))[0]
+                            for i, p in enumerate(parts)])
+        assert_hits_match(h, ref)
+        alone.append(h)
+        s.close()
+    # device inputs and outputs prepared up front; each thread only launches
+    streams = [torch.cuda.Stream() for _ in work]
+    objs, dev, outs = [], [], []
+    for kw, ref, parts in work:
+        objs.append(tpx.Stream(max(len(p) for p in parts), **kw))
+        dev.append([torch.from_numpy(p.view(np.int64)).cuda() for p in parts])
+        outs.append([torch.empty((max(len(p), 1024), 48), dtype=torch.uint8, device="cuda")
+                     for p in parts])
+    torch.cuda.synchronize()
+    counts = [[None] * len(d) for d in dev]
+    errors = []
+
+    def drive(k):
+        try:
+            with torch.cuda.stream(streams[k]):
+                for i, (pk, hb) in enumerate(zip(dev[k], outs[k])):
+                    rc, n, _ = objs[k].process_raw(pk, i == len(dev[k]) - 1, hb, hb.shape[0])
+                    if rc != 0:
+                        raise RuntimeError(f"stream {k} chunk {i}: status {rc}")
+                    counts[k][i] = n
+        except Exception as e:  # reported by the main thread
+            errors.append(e)
+
+    th = [threading.Thread(target=drive, args=(k,)) for k in range(len(work))]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    torch.cuda.synchronize()
+    assert not errors, errors
+    for k in range(len(work)):
+        h = np.concatenate([tpx.hits_to_numpy(hb, n) for hb, n in zip(outs[k], counts[k])])
+        assert h.tobytes() == alone[k].tobytes()
+        objs[k].close()
+
+
 def test_stream_out_of_order_takes_general_path(tpx, orc):
     """A kept pixel of one shot reported after pixels of the next shot: the
     events are not in shot order and the general sorting path must give the
