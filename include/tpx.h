@@ -224,19 +224,34 @@ const char* tpx_stream_stage_name(size_t i);
 /* Segment stride of the stream's clustering: consecutive shots are packed
  * into segments that start every q kept events (a segment ends at the end of
  * the shot that crosses the next start), one workgroup per segment; 64 <= q
- * <= 2048, default 1024.  Results do not depend on q, only the time.
+ * <= 4096, default 1024.  Results do not depend on q, only the time.
+ *
+ * Kernel of the stream's clustering (radius 1): tpx_stream_kernel_count()
+ * variants of the fused segment kernel (components, moments and hits of a
+ * segment in one workgroup; they differ in the height of the LDS pixel image
+ * and the workgroup size; tpx_stream_kernel_name names them), or -1 for the
+ * staged kernels (components, then moments and hits in a second launch).
+ * Other radii always take the staged kernels.  Results do not depend on the
+ * kernel.  Default 0.
+ *
  * tpx_stream_autotune (the sweep of the uneven-shot workload) runs the chunk
- * at every candidate q (best of `reps`, timed with HIP events on `stream`),
- * restoring the stream state before each run and after the last, writes the
- * times to ms_h (host, n_cand, may be NULL) and keeps the fastest q
- * (*best_h).  hits / hit_cap as in tpx_process_stream; on an error the
- * stream keeps its state and its former q. */
+ * at every pair of candidate q (cand_h[n_cand]) and kernel (kern_h[n_kern];
+ * NULL = the stream's current kernel only), best of `reps` each, timed with
+ * HIP events on `stream`, restoring the stream state before each run and
+ * after the last; writes the times to ms_h (host, [n_kern][n_cand], may be
+ * NULL) and keeps the fastest pair (*best_h, *best_kern_h, which may be
+ * NULL).  hits / hit_cap as in tpx_process_stream; on an error the stream
+ * keeps its state, its former q and its former kernel. */
 tpx_status tpx_stream_set_segment(tpx_stream* s, uint32_t q);
 uint32_t tpx_stream_get_segment(const tpx_stream* s);
+int tpx_stream_kernel_count(void);
+const char* tpx_stream_kernel_name(int k);
+tpx_status tpx_stream_set_kernel(tpx_stream* s, int k);
+int tpx_stream_get_kernel(const tpx_stream* s);
 tpx_status tpx_stream_autotune(tpx_stream* s, const uint64_t* chunk, size_t n_pkts, int flush,
                                tpx_hit* hits, size_t hit_cap, const uint32_t* cand_h,
-                               size_t n_cand, int reps, float* ms_h, uint32_t* best_h,
-                               void* stream);
+                               size_t n_cand, const int* kern_h, size_t n_kern, int reps,
+                               float* ms_h, uint32_t* best_h, int* best_kern_h, void* stream);
 
 /* Continuous batching over one stream (the streaming workload's chunked
  * acquisition, Sec. IV: the unwrap runs across the whole stream).  Chunks are
@@ -334,6 +349,12 @@ tpx_status tpx_patches(tpx_events ev, const uint32_t* labels, size_t n_ev, const
  *                       TPX_EINVAL without such a call or with another
  *                       count.  Synchronises. */
 size_t tpx_stream_patch_workspace_bytes(size_t n_hits);
+/*   tpx_stream_set_patches  enable (1) or disable (0) recording, during each
+ *                       tpx_process_stream call on s, the hit of every event
+ *                       (4 bytes per event) that tpx_stream_patches needs
+ *                       after the fused kernel; enable it before the call
+ *                       whose hits are to be patched. */
+tpx_status tpx_stream_set_patches(tpx_stream* s, int enable);
 tpx_status tpx_stream_patches(tpx_stream* s, const tpx_hit* hits, size_t n_hits, uint16_t* feat,
                               void* ws, size_t ws_bytes, void* stream);
 size_t tpx_mlp_workspace_bytes(size_t batch);

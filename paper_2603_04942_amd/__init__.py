@@ -73,7 +73,9 @@ EXPORTS = ("tpx_params_default", "tpx_unwrap_state_init", "tpx_workspace_bytes",
            "tpx_patch_workspace_bytes", "tpx_patches", "tpx_mlp_workspace_bytes",
            "tpx_mlp_forward", "tpx_mlp_grad", "tpx_mlp_adam", "tpx_mlp_refine",
            "tpx_stream_set_segment", "tpx_stream_get_segment", "tpx_stream_autotune",
-           "tpx_stream_patch_workspace_bytes", "tpx_stream_patches")
+           "tpx_stream_patch_workspace_bytes", "tpx_stream_patches", "tpx_stream_set_patches",
+           "tpx_stream_kernel_count", "tpx_stream_kernel_name", "tpx_stream_set_kernel",
+           "tpx_stream_get_kernel")
 
 _lib = None
 
@@ -124,8 +126,19 @@ def load(path=LIB_PATH):
     lib.tpx_stream_set_segment.restype = I
     lib.tpx_stream_get_segment.argtypes = [P]
     lib.tpx_stream_get_segment.restype = ctypes.c_uint32
-    lib.tpx_stream_autotune.argtypes = [P, P, S, ctypes.c_int, P, S, P, S, ctypes.c_int, P, P, P]
+    lib.tpx_stream_autotune.argtypes = [P, P, S, ctypes.c_int, P, S, P, S, P, S, ctypes.c_int, P,
+                                        P, P, P]
     lib.tpx_stream_autotune.restype = I
+    lib.tpx_stream_kernel_count.argtypes = []
+    lib.tpx_stream_kernel_count.restype = ctypes.c_int
+    lib.tpx_stream_kernel_name.argtypes = [ctypes.c_int]
+    lib.tpx_stream_kernel_name.restype = ctypes.c_char_p
+    lib.tpx_stream_set_kernel.argtypes = [P, ctypes.c_int]
+    lib.tpx_stream_set_kernel.restype = I
+    lib.tpx_stream_get_kernel.argtypes = [P]
+    lib.tpx_stream_get_kernel.restype = ctypes.c_int
+    lib.tpx_stream_set_patches.argtypes = [P, ctypes.c_int]
+    lib.tpx_stream_set_patches.restype = I
     lib.tpx_stream_patch_workspace_bytes.argtypes = [S]
     lib.tpx_stream_patch_workspace_bytes.restype = S
     lib.tpx_stream_patches.argtypes = [P, P, S, P, P, S, P]
@@ -322,10 +335,21 @@ def local_maxima_raw(ev, trig, hits, hit_cap, ws, params=None):
     return rc, int(nh.value)
 
 
-class Stream:
-    """tpx_stream: decode -> cluster -> centroid over consecutive chunks."""
+def kernel_count():
+    """Fused clustering-kernel variants (kernel -1 = the staged kernels)."""
+    return int(load().tpx_stream_kernel_count())
 
-    def __init__(self, max_chunk_pkts, params=None, **kw):
+
+def kernel_name(k):
+    return load().tpx_stream_kernel_name(int(k)).decode()
+
+
+class Stream:
+    """tpx_stream: decode -> cluster -> centroid over consecutive chunks.
+    kernel: clustering kernel (None = the library's default); patches: record
+    the hit of every event so that patches() can follow each call."""
+
+    def __init__(self, max_chunk_pkts, params=None, kernel=None, patches=False, **kw):
         self.torch = _torch()
         self.lib = load()
         self.params = params or make_params(**kw)
@@ -335,6 +359,10 @@ class Stream:
                                           ctypes.byref(h)), "tpx_stream_create")
         self.h = h
         self.max_chunk = max_chunk_pkts
+        if kernel is not None:
+            self.set_kernel(kernel)
+        if patches:
+            self.set_patches(True)
 
     def close(self):
         if getattr(self, "h", None):
@@ -377,18 +405,34 @@ class Stream:
     def segment(self):
         return int(self.lib.tpx_stream_get_segment(self.h))
 
-    def autotune(self, chunk, flush, candidates, hits, hit_cap, reps=3):
-        """tpx_stream_autotune: (best stride, {stride: ms})."""
+    def set_patches(self, enable=True):
+        """Record the hit of every event in the following calls (needed by
+        patches() after the fused kernel)."""
+        _check(self.lib.tpx_stream_set_patches(self.h, int(enable)), "tpx_stream_set_patches")
+
+    def set_kernel(self, k):
+        _check(self.lib.tpx_stream_set_kernel(self.h, int(k)), "tpx_stream_set_kernel")
+
+    def kernel(self):
+        return int(self.lib.tpx_stream_get_kernel(self.h))
+
+    def autotune(self, chunk, flush, candidates, hits, hit_cap, reps=3, kernels=None):
+        """tpx_stream_autotune over strides x kernels (None: the current
+        kernel only): (best stride, best kernel, {(kernel, stride): ms})."""
         torch = self.torch
         pk = _u64(torch, chunk)
         cand = (ctypes.c_uint32 * len(candidates))(*candidates)
-        ms = (ctypes.c_float * len(candidates))()
-        best = ctypes.c_uint32()
+        ks = list(kernels) if kernels is not None else [self.kernel()]
+        kern = (ctypes.c_int * len(ks))(*ks) if kernels is not None else None
+        ms = (ctypes.c_float * (len(candidates) * len(ks)))()
+        best, best_k = ctypes.c_uint32(), ctypes.c_int()
         rc = self.lib.tpx_stream_autotune(self.h, _ptr(pk), pk.numel(), int(flush), _ptr(hits),
-                                          hit_cap, cand, len(candidates), reps, ms,
-                                          ctypes.byref(best), _stream(torch))
+                                          hit_cap, cand, len(candidates), kern, len(ks), reps, ms,
+                                          ctypes.byref(best), ctypes.byref(best_k), _stream(torch))
         _check(rc, "tpx_stream_autotune")
-        return int(best.value), {int(c): float(m) for c, m in zip(candidates, ms)}
+        times = {(int(k), int(c)): float(ms[j * len(candidates) + i])
+                 for j, k in enumerate(ks) for i, c in enumerate(candidates)}
+        return int(best.value), int(best_k.value), times
 
     def patches(self, hits, n_hits):
         """tpx_stream_patches: bfloat16 patches (int16 tensor [n_hits, 98]) of
@@ -482,9 +526,9 @@ class Service:
             pass
 
 
-def process_stream(packets, flush=True, **kw):
+def process_stream(packets, flush=True, kernel=None, **kw):
     """One-shot helper: the whole packet buffer as a single flushed chunk."""
-    s = Stream(max(int(len(packets)), 1), **kw)
+    s = Stream(max(int(len(packets)), 1), kernel=kernel, **kw)
     try:
         return s.process(packets, flush=flush)
     finally:

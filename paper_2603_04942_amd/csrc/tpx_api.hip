@@ -39,7 +39,8 @@ namespace {
     } while (0)
 
 constexpr uint32_t kQ = 1024;           // segment stride (events), default
-constexpr uint32_t kQMin = 64, kQMax = 2048;  // strides a stream accepts
+constexpr int kDefaultFused = 0;        // fused-kernel variant of a new stream
+constexpr uint32_t kQMin = 64, kQMax = 4096;  // strides a stream accepts
 constexpr uint32_t kQPaper = 512;       // segment stride of the paper mode: a shot of up to
                                         // 1,536 events always fits one 2,048-event segment
 constexpr int kStages = 7;              // timed stages of the stream fast path
@@ -516,6 +517,8 @@ struct tpx_stream {
     uint32_t *seg_lo, *seg_cnt, *seg_off, *rank;
     uint32_t* big[6];
     uint64_t* g_acc;
+    tpx_hit* hits_tmp;      // staged hits of the fused kernel
+    uint32_t* hit_index;    // hit of every event of the last call (when kept)
     // committed host state
     int64_t pix_epoch, tdc_epoch;
     uint64_t pix_last, tdc_last;
@@ -530,6 +533,9 @@ struct tpx_stream {
     uint64_t carry_last1;   // window index of the last carried event + 1 (0 = none)
     int cur;
     uint32_t q;             // segment stride of the clustering (events)
+    int kernel;             // fused-kernel variant, or -1: staged cluster + centroid kernels
+    int keep_hit_index;     // record the hit of every event (tpx_stream_patches)
+    int last_fused;         // the last call took the fused kernel
     // the last successful call's clustering (its events, ranks and segment
     // offsets stay in place until the next call): patches of its hits
     ClusterArgs last_c;
@@ -565,6 +571,10 @@ void free_stream(tpx_stream* s) {
     delete s;
 }
 
+void mark(tpx_stream* s, int i, hipStream_t hs) {
+    if (s->timing) (void)hipEventRecord(s->tev[i], hs);
+}
+
 ClusterArgs stream_cluster_args(tpx_stream* s, tpx_hit* hits, uint64_t hit_cap) {
     ClusterArgs a{};
     a.q = s->q;
@@ -589,7 +599,38 @@ ClusterArgs stream_cluster_args(tpx_stream* s, tpx_hit* hits, uint64_t hit_cap) 
     a.g_sl = s->big[4];
     a.g_xy = s->big[5];
     a.g_acc = s->g_acc;
+    a.hits_tmp = s->hits_tmp;
+    a.hit_index = s->keep_hit_index ? s->hit_index : nullptr;
     return a;
+}
+
+// fused kernel for radius 1 (times of flight in 16 bits) unless the staged
+// kernels were asked for
+bool use_fused(const tpx_stream* s) {
+    return s->p.dxy == 1 && s->p.tof_max_ticks < 65536 && s->kernel >= 0;
+}
+
+// components and hits of the closed events: one fused launch, or the staged
+// cluster -> prefix -> centroid kernels
+void stream_cluster(tpx_stream* s, const ClusterArgs& c, uint64_t grid, hipStream_t hs) {
+    s->last_c = c;
+    s->last_grid = grid;
+    s->last_fused = use_fused(s);
+    if (s->last_fused) {
+        mark(s, 4, hs);
+        launch_cluster_fused(c, grid, s->kernel, hs);
+        mark(s, 5, hs);
+        launch_scan_u32(s->seg_cnt, s->seg_off, 0, &s->res->n_seg, s->block_tmp, hs);
+        launch_hit_compact(c, grid, hs);
+        mark(s, 6, hs);
+        return;
+    }
+    mark(s, 4, hs);
+    launch_cluster(c, false, grid, hs);
+    mark(s, 5, hs);
+    launch_scan_u32(s->seg_cnt, s->seg_off, 0, &s->res->n_seg, s->block_tmp, hs);
+    launch_seg_centroid(c, grid, hs);
+    mark(s, 6, hs);
 }
 
 AssignArgs stream_assign_args(tpx_stream* s, const uint64_t* chunk, uint64_t n) {
@@ -615,9 +656,6 @@ AssignArgs stream_assign_args(tpx_stream* s, const uint64_t* chunk, uint64_t n) 
     return a;
 }
 
-void mark(tpx_stream* s, int i, hipStream_t hs) {
-    if (s->timing) (void)hipEventRecord(s->tev[i], hs);
-}
 
 // decode front end of one chunk (shared by both paths)
 void stream_front(tpx_stream* s, const uint64_t* chunk, uint64_t n, hipStream_t hs) {
@@ -661,15 +699,7 @@ tpx_status stream_fast(tpx_stream* s, const uint64_t* chunk, uint64_t n, int flu
     c.skip = &s->res->unsorted;
     c.seg_lo = s->seg_lo;
     launch_seg_table(c.grp_off, c.n_grp_dev, c.n_ev_dev, c.skip, s->q, rows, s->seg_lo, s->res, hs);
-    mark(s, 4, hs);
-    const uint64_t grid = cluster_grid(s->n_carry + n, s->q);
-    s->last_c = c;
-    s->last_grid = grid;
-    launch_cluster(c, false, grid, hs);
-    mark(s, 5, hs);
-    launch_scan_u32(s->seg_cnt, s->seg_off, 0, &s->res->n_seg, s->block_tmp, hs);
-    launch_seg_centroid(c, grid, hs);
-    mark(s, 6, hs);
+    stream_cluster(s, c, cluster_grid(s->n_carry + n, s->q), hs);
     const int nx = 1 - s->cur;
     launch_carry_out(s->ev, nullptr, nullptr, s->shot_off, &s->res->n_groups, &s->res->n_close_ev,
                      &s->res->n_kept, s->c_gidx[s->cur], s->n_carry, s->ev_next, s->c_ev[nx],
@@ -714,12 +744,7 @@ tpx_status stream_general(tpx_stream* s, const uint64_t* chunk, uint64_t n, int 
     c.n_grp_dev = &s->res->n_close_list;
     c.seg_lo = s->seg_lo;
     launch_seg_table(c.grp_off, c.n_grp_dev, c.n_ev_dev, nullptr, s->q, N, s->seg_lo, s->res, hs);
-    const uint64_t grid = cluster_grid(N, s->q);
-    s->last_c = c;
-    s->last_grid = grid;
-    launch_cluster(c, false, grid, hs);
-    launch_scan_u32(s->seg_cnt, s->seg_off, 0, &s->res->n_seg, s->block_tmp, hs);
-    launch_seg_centroid(c, grid, hs);
+    stream_cluster(s, c, cluster_grid(N, s->q), hs);
     const int nx = 1 - s->cur;
     launch_carry_out(s->ev_sorted, vo, ko, nullptr, nullptr, &s->res->n_close_ev, &s->res->n_kept,
                      s->c_gidx[s->cur], s->n_carry, s->ev_next, s->c_ev[nx], s->c_shot[nx],
@@ -745,6 +770,7 @@ tpx_status tpx_stream_create(const tpx_params* p_h, size_t max_chunk_pkts, tpx_s
     s->ev_cap = n + s->carry_cap;
     s->tab_cap = n + s->carry_cap + 2;
     s->q = kQ;
+    s->kernel = kDefaultFused;
     s->seg_cap = s->ev_cap / kQMin + 4;
     if (hipHostMalloc((void**)&s->res_h, sizeof(DevResults), 0) != hipSuccess) {
         (void)hipGetLastError();
@@ -793,6 +819,8 @@ tpx_status tpx_stream_create(const tpx_params* p_h, size_t max_chunk_pkts, tpx_s
     ALLOC(s->rank, s->ev_cap);
     for (int k = 0; k < 6; ++k) ALLOC(s->big[k], s->ev_cap);
     ALLOC(s->g_acc, 8 * s->ev_cap);
+    ALLOC(s->hits_tmp, s->ev_cap);
+    ALLOC(s->hit_index, s->ev_cap);
 #undef ALLOC
     s->pix_epoch = p_h->pix_epoch0;
     s->tdc_epoch = p_h->tdc_epoch0;
@@ -1002,6 +1030,29 @@ tpx_status tpx_stream_set_segment(tpx_stream* s, uint32_t q) {
 
 uint32_t tpx_stream_get_segment(const tpx_stream* s) { return s ? s->q : 0; }
 
+int tpx_stream_kernel_count(void) { return fused_variants(); }
+
+const char* tpx_stream_kernel_name(int k) {
+    return k < 0 ? "staged cluster and centroid kernels" : fused_variant_name(k);
+}
+
+tpx_status tpx_stream_set_kernel(tpx_stream* s, int k) {
+    if (!s) return fail(TPX_EINVAL, "stream is NULL");
+    if (k < -1 || k >= fused_variants())
+        return fail(TPX_EINVAL, "kernel %d outside [-1, %d)", k, fused_variants());
+    s->kernel = k;
+    return TPX_OK;
+}
+
+int tpx_stream_get_kernel(const tpx_stream* s) { return s ? s->kernel : -2; }
+
+tpx_status tpx_stream_set_patches(tpx_stream* s, int enable) {
+    if (!s) return fail(TPX_EINVAL, "stream is NULL");
+    s->keep_hit_index = enable ? 1 : 0;
+    s->last_ok = 0;  // the last call's events carry no hit index yet
+    return TPX_OK;
+}
+
 size_t tpx_stream_patch_workspace_bytes(size_t n_hits) { return n_hits * 99 * 4 + 256; }
 
 tpx_status tpx_stream_patches(tpx_stream* s, const tpx_hit* hits, size_t n_hits, uint16_t* feat,
@@ -1014,10 +1065,14 @@ tpx_status tpx_stream_patches(tpx_stream* s, const tpx_hit* hits, size_t n_hits,
     if (n_hits && (!hits || !feat)) return fail(TPX_EINVAL, "hits or feat is NULL");
     if (!ws || ws_bytes < tpx_stream_patch_workspace_bytes(n_hits))
         return fail(TPX_EINVAL, "workspace too small");
+    if (s->last_fused && !s->keep_hit_index)
+        return fail(TPX_EINVAL, "tpx_stream_set_patches(s, 1) must precede the call whose hits "
+                    "are patched");
     if (n_hits == 0) return TPX_OK;
     hipStream_t hs = (hipStream_t)stream;
     int* err = (int*)((char*)ws + n_hits * 99 * 4);
-    launch_stream_patches(s->last_c, s->last_grid, hits, n_hits, (uint32_t*)ws, feat, err, hs);
+    launch_stream_patches(s->last_c, s->last_grid, s->last_fused, hits, n_hits, (uint32_t*)ws,
+                          feat, err, hs);
     int e = 0;
     HIPCHK(hipMemcpyAsync(&e, err, 4, hipMemcpyDeviceToHost, hs));
     HIPCHK(hipStreamSynchronize(hs));
@@ -1030,13 +1085,19 @@ tpx_status tpx_stream_patches(tpx_stream* s, const tpx_hit* hits, size_t n_hits,
 // fastest stride and leaves the stream state as it was.
 tpx_status tpx_stream_autotune(tpx_stream* s, const uint64_t* chunk, size_t n_pkts, int flush,
                                tpx_hit* hits, size_t hit_cap, const uint32_t* cand_h,
-                               size_t n_cand, int reps, float* ms_h, uint32_t* best_h,
-                               void* stream) {
+                               size_t n_cand, const int* kern_h, size_t n_kern, int reps,
+                               float* ms_h, uint32_t* best_h, int* best_kern_h, void* stream) {
     if (!s || !cand_h || !best_h) return fail(TPX_EINVAL, "NULL argument");
     if (n_cand == 0 || reps < 1) return fail(TPX_EINVAL, "no candidates or repetitions");
     for (size_t i = 0; i < n_cand; ++i)
         if (cand_h[i] < kQMin || cand_h[i] > kQMax)
             return fail(TPX_EINVAL, "segment stride %u outside [%u, %u]", cand_h[i], kQMin, kQMax);
+    const int k_now = s->kernel;
+    const size_t nk = kern_h ? n_kern : 1;
+    if (nk == 0) return fail(TPX_EINVAL, "no kernel candidates");
+    for (size_t j = 0; kern_h && j < nk; ++j)
+        if (kern_h[j] < -1 || kern_h[j] >= fused_variants())
+            return fail(TPX_EINVAL, "kernel %d outside [-1, %d)", kern_h[j], fused_variants());
     size_t bytes = 0;
     tpx_status rc = tpx_stream_get_state(s, nullptr, &bytes);
     if (rc) return rc;
@@ -1053,26 +1114,31 @@ tpx_status tpx_stream_autotune(tpx_stream* s, const uint64_t* chunk, size_t n_pk
     }
     float best = 3.0e38f;
     uint32_t best_q = q0;
-    for (size_t i = 0; i < n_cand && rc == TPX_OK; ++i) {
-        s->q = cand_h[i];
-        float t_min = 3.0e38f;
-        for (int r = 0; r < reps && rc == TPX_OK; ++r) {
-            if ((rc = tpx_stream_set_state(s, saved.data(), bytes))) break;
-            size_t nh = 0;
-            float ms = 0.f;
-            if (hipEventRecord(e0, hs) != hipSuccess) rc = fail(TPX_EHIP, "event record failed");
-            if (!rc) rc = tpx_process_stream(s, chunk, n_pkts, flush, hits, hit_cap, &nh, nullptr,
-                                             stream);
-            if (!rc && (hipEventRecord(e1, hs) != hipSuccess ||
-                        hipEventSynchronize(e1) != hipSuccess ||
-                        hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
-                rc = fail(TPX_EHIP, "event timing failed");
-            if (!rc) t_min = std::min(t_min, ms);
-        }
-        if (ms_h) ms_h[i] = t_min;
-        if (!rc && t_min < best) {
-            best = t_min;
-            best_q = cand_h[i];
+    int best_k = k_now;
+    for (size_t j = 0; j < nk && rc == TPX_OK; ++j) {
+        s->kernel = kern_h ? kern_h[j] : k_now;
+        for (size_t i = 0; i < n_cand && rc == TPX_OK; ++i) {
+            s->q = cand_h[i];
+            float t_min = 3.0e38f;
+            for (int r = 0; r < reps && rc == TPX_OK; ++r) {
+                if ((rc = tpx_stream_set_state(s, saved.data(), bytes))) break;
+                size_t nh = 0;
+                float ms = 0.f;
+                if (hipEventRecord(e0, hs) != hipSuccess) rc = fail(TPX_EHIP, "event record failed");
+                if (!rc) rc = tpx_process_stream(s, chunk, n_pkts, flush, hits, hit_cap, &nh, nullptr,
+                                                 stream);
+                if (!rc && (hipEventRecord(e1, hs) != hipSuccess ||
+                            hipEventSynchronize(e1) != hipSuccess ||
+                            hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                    rc = fail(TPX_EHIP, "event timing failed");
+                if (!rc) t_min = std::min(t_min, ms);
+            }
+            if (ms_h) ms_h[j * n_cand + i] = t_min;
+            if (!rc && t_min < best) {
+                best = t_min;
+                best_q = cand_h[i];
+                best_k = s->kernel;
+            }
         }
     }
     (void)hipEventDestroy(e0);
@@ -1080,9 +1146,11 @@ tpx_status tpx_stream_autotune(tpx_stream* s, const uint64_t* chunk, size_t n_pk
     const tpx_status rs = tpx_stream_set_state(s, saved.data(), bytes);
     s->n_fallback = fb0;
     s->q = rc ? q0 : best_q;
+    s->kernel = rc ? k_now : best_k;
     if (rc) return rc;
     if (rs) return rs;
     *best_h = best_q;
+    if (best_kern_h) *best_kern_h = best_k;
     return TPX_OK;
 }
 

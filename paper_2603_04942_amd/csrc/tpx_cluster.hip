@@ -679,7 +679,6 @@ __global__ __launch_bounds__(kWG, 2) void k_cluster(ClusterArgs a) {
     } else {
         seg_big<kEvent>(a, lds, scan_tmp, sg, k);
     }
-    if (tid == 0) atomicMax(&a.res->max_segment, (unsigned long long)sg.n);
 }
 
 uint64_t cluster_grid(uint64_t max_events, uint32_t q) { return max_events / q + 2; }
@@ -1053,6 +1052,622 @@ void launch_paper(const ClusterArgs& a, const uint64_t* trig, bool write, uint64
         hipLaunchKernelGGL(k_paper<true>, dim3((unsigned)grid), dim3(kWG), 0, s, a, trig);
     else
         hipLaunchKernelGGL(k_paper<false>, dim3((unsigned)grid), dim3(kWG), 0, s, a, trig);
+}
+
+}  // namespace tpx
+
+namespace tpx {
+
+// ================================================ fused stream-mode kernel
+// Radius 1, stream mode: one workgroup per segment finds the segment's
+// components (Eqs. 3-5 closed transitively), their exact integer moments and
+// their hits (Eq. 9) without leaving the workgroup: the events are read from
+// HBM once and the hits written once, into a staging buffer at the segment's
+// own range (hit r of the segment at its first event index + r), from which
+// a copy kernel moves them to their final place after a prefix sum of the
+// segments' component counts.  No workgroup ever waits for another.
+//
+// LDS: an image of slot-list heads (u16, slot = (y mod 2^kYB, x)); every
+// event is pushed on the list of its slot by a compare-and-swap of the 32-bit
+// word that holds the slot, so a slot's list holds all its events after one
+// pass.  Per event a 32-bit key, the
+// union-find parent, the pixel address and ToT, and the list link (after the
+// load no phase touches global memory until the hits are written).  The key holds the time of flight
+// (16 bits; the kernel is used when every kept time of flight fits), the
+// high bits of y that the slot does not hold, and the first position of the
+// event's group (shot) in the segment: two events in slots of a 3x3 box are
+// neighbours when their keys agree above the time bits (same group, exact
+// row) and their times differ by at most the window.  After the unions the
+// image region holds the per-component accumulators.
+//
+// Phases (each ends at a workgroup barrier reached by every thread):
+//   1. load + push on the slot lists;
+//   2. each event unites with its neighbours in the backward half of its box
+//      (the row above, the slot to its left, and earlier events of its own
+//      slot), so every edge is seen once; lock-free union-find that hooks
+//      the larger root under the smaller by compare-and-swap;
+//   3. final roots (the smallest position of each component = its label);
+//   4. ranks of the roots in position order;
+//   5. moments per component (LDS atomics);
+//   6. hits, staged.
+// A segment over kSeg events keeps its per-event arrays in global scratch;
+// a segment with more components than the accumulators hold sums them in
+// global scratch; both in the same workgroup.
+
+template <int kYB, int kNT, int kSeg>
+struct FusedCfg {
+    static constexpr int kSlots = 256 << kYB;      // u16 list heads
+    static constexpr uint32_t kYMask = (1u << kYB) - 1u;
+    static constexpr int kYHB = 8 - kYB;           // bits of y above the slot's
+    static constexpr int kGShift = 16 + kYHB;      // group start above the time and y bits
+    static constexpr int kE = kSeg / kNT;          // events per thread
+    static constexpr int kNW = kNT / 64;
+    static constexpr int kOffKey = kSlots * 2;         // u32[kSeg]
+    static constexpr int kOffPar = kOffKey + 4 * kSeg; // u32[kSeg]
+    static constexpr int kOffXyt = kOffPar + 4 * kSeg; // u32[kSeg]: x | y << 8 | ToT << 16
+    static constexpr int kOffNxt = kOffXyt + 4 * kSeg; // u16[kSeg]: list link, later root rank
+    static constexpr int kBytes = kOffNxt + 2 * kSeg;
+    // accumulators in the image region: u32 W, SX, SY, CNT, TMIN, P; u64 ST
+    static constexpr int kHitCap = kSlots * 2 / 32;
+    static_assert(kSeg % kNT == 0 && kSeg <= (1 << (32 - kGShift)) && kSeg < 65535,
+                  "segment capacity");
+    // the global-memory path keeps a u32 image of list heads in the same LDS
+    static constexpr int kBigYB = (1024 << 6) <= kBytes ? 6 : (1024 << 5) <= kBytes ? 5 : 4;
+    static constexpr int kBigSlots = 256 << kBigYB;
+    static_assert(kBigSlots * 4 <= kBytes, "image of the global-memory path");
+    __device__ static uint32_t big_slot(uint32_t x, uint32_t y) {
+        return ((y & ((1u << kBigYB) - 1u)) << 8) | x;
+    }
+    __device__ static uint32_t slot(uint32_t x, uint32_t y) { return ((y & kYMask) << 8) | x; }
+    // key bits above the time: group start and the high bits of y
+    __device__ static uint32_t hi(uint32_t gs, uint32_t y) { return (gs << kYHB) | (y >> kYB); }
+};
+
+// Global accumulators of component c of the segment starting at e0: 8 words
+// (W, count, Sx, Sy, St, min t, root position).
+__device__ inline unsigned long long* gacc(const ClusterArgs& a, uint64_t e0, uint32_t c) {
+    return (unsigned long long*)a.g_acc + 8 * (e0 + c);
+}
+
+__device__ inline void gacc_add(const ClusterArgs& a, unsigned long long* q, uint64_t pk) {
+    const uint32_t x = ev_x(pk), y = ev_y(pk), tot = ev_tot(pk), t = ev_t(pk);
+    atomicAdd(q + 0, (unsigned long long)tot);
+    atomicAdd(q + 1, 1ull);
+    atomicAdd(q + 2, (unsigned long long)(tot * x));
+    atomicAdd(q + 3, (unsigned long long)(tot * y));
+    atomicAdd(q + 4, (unsigned long long)time_term(a, tot, t));
+    atomicMin(q + 5, (unsigned long long)t);
+}
+
+__device__ inline void gacc_add_plain(const ClusterArgs& a, unsigned long long* q, uint64_t pk) {
+    atomicAdd(q + 2, (unsigned long long)ev_x(pk));
+    atomicAdd(q + 3, (unsigned long long)ev_y(pk));
+    atomicAdd(q + 4, (unsigned long long)time_term1(a, ev_tot(pk), ev_t(pk)));
+}
+
+__device__ inline unsigned long long gacc_ld(unsigned long long* q) {
+    return __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Staged hit of component c (root = smallest position p in the segment).
+__device__ inline void fused_emit(const ClusterArgs& a, const Seg& sg, const uint32_t* goff,
+                                  bool goff_lds, uint32_t c, uint32_t p, uint64_t W, uint64_t cnt,
+                                  uint64_t sx, uint64_t sy, uint64_t st, uint32_t tmin) {
+    const uint32_t ng = sg.g_hi - sg.g_lo;
+    const uint32_t pos = (uint32_t)(sg.e0 + p);
+    const uint32_t g = goff_lds ? sg.g_lo + group_of(goff, 0, ng, pos)
+                                : group_of(a.grp_off, sg.g_lo, sg.g_hi, pos);
+    ClusterArgs b = a;  // the staging buffer stands in for the output
+    b.hits = a.hits_tmp;
+    b.hit_cap = ~0ull;
+    write_hit(b, sg.e0 + c, g, W, cnt, sx, sy, st, tmin, gidx_of(a, sg.e0 + p));
+}
+
+// Components of a segment of more than C::kSeg events, per-event arrays in
+// global scratch, the image in LDS.  Leaves the rank of every event's
+// component in a.rank[e0 + i] and returns the component count.
+template <class C, int kNT>
+__device__ uint32_t fused_big(const ClusterArgs& a, uint8_t* lds, uint32_t* scan_tmp,
+                              const uint32_t* goff, bool goff_lds, const Seg& sg) {
+    uint32_t* img = (uint32_t*)lds;
+    const uint64_t e0 = sg.e0;
+    const uint32_t n = sg.n, dt = a.dt;
+    uint32_t* par = a.g_parent + e0;
+    uint32_t* root = a.g_chain + e0;
+    uint32_t* nxt = a.g_next + e0;
+    uint32_t* tt = a.g_t + e0;
+    uint32_t* gs = a.g_sl + e0;
+    uint32_t* xy = a.g_xy + e0;
+    const int tid = threadIdx.x;
+    unsigned long long* err = &a.res->err;
+    if (tid == 0) atomicAdd(&a.res->big_segments, 1ull);
+    for (int i = tid; i < C::kBigSlots / 4; i += kNT)
+        ((uint4*)img)[i] = make_uint4(~0u, ~0u, ~0u, ~0u);
+    __syncthreads();
+    for (uint32_t i = tid; i < n; i += kNT) {
+        const uint32_t p = (uint32_t)(e0 + i);
+        const uint32_t g = goff_lds ? sg.g_lo + group_of(goff, 0, sg.g_hi - sg.g_lo, p)
+                                    : group_of(a.grp_off, sg.g_lo, sg.g_hi, p);
+        const Ev e = load_event<false>(a, e0 + i, g, e0, err);
+        par[i] = i;
+        tt[i] = e.t;
+        gs[i] = e.gs;
+        xy[i] = e.x | (e.y << 8);
+        nxt[i] = atomicExch(&img[C::big_slot(e.x, e.y)], i);
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < n; i += kNT) {
+        const uint32_t v = xy[i];
+        const int x = (int)(v & 255u), y = (int)(v >> 8);
+        const uint32_t t = tt[i], g = gs[i];
+        for (int s = 0; s < 9; ++s) {
+            const int nx = x + s % 3 - 1, ny = y + s / 3 - 1;
+            if (nx < 0 || nx > 255 || ny < 0 || ny > 255) continue;
+            uint32_t j = img[C::big_slot((uint32_t)nx, (uint32_t)ny)], steps = 0;
+            while (j != kNone32) {
+                if (j < i && gs[j] == g && absdiff(tt[j], t) <= dt &&
+                    xy[j] == ((uint32_t)nx | ((uint32_t)ny << 8)))
+                    uf_unite(par, i, j, n, err);
+                if (++steps > n) {
+                    atomicOr(err, (unsigned long long)kErrLoopChain);
+                    break;
+                }
+                j = nxt[j];
+            }
+        }
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < n; i += kNT) root[i] = uf_find(par, i, n, err);
+    __syncthreads();
+    uint32_t running = 0;
+    const uint32_t rounds = (n + kNT - 1) / kNT;
+    for (uint32_t rd = 0; rd < rounds; ++rd) {
+        const uint32_t i = rd * kNT + tid;
+        uint32_t tot;
+        const bool is_root = i < n && root[i] == i;
+        const uint32_t rk = running + wg_flag_scan<kNT>(is_root, scan_tmp, &tot);
+        if (is_root) par[i] = rk;  // parents are no longer needed: keep the rank
+        running += tot;
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < n; i += kNT) a.rank[e0 + i] = par[root[i]];
+    return running;
+}
+
+template <int kYB, int kNT, int kSeg>
+__global__ __launch_bounds__(kNT) void k_cluster_fused(ClusterArgs a) {
+    using C = FusedCfg<kYB, kNT, kSeg>;
+    constexpr int kE = C::kE;
+    __shared__ __attribute__((aligned(16))) uint8_t lds[C::kBytes];
+    __shared__ uint32_t scan_tmp[C::kNW + 1];
+    __shared__ uint32_t goff[kNT + 1];
+    uint32_t* img = (uint32_t*)lds;  // as 32-bit words: two u16 heads each
+    const uint16_t* head16 = (const uint16_t*)lds;
+    uint32_t* key = (uint32_t*)(lds + C::kOffKey);
+    uint32_t* par = (uint32_t*)(lds + C::kOffPar);
+    uint32_t* xyt = (uint32_t*)(lds + C::kOffXyt);
+    uint16_t* nxt = (uint16_t*)(lds + C::kOffNxt);
+    // accumulators (after the unions)
+    uint32_t* aW = img;
+    uint32_t* aX = img + C::kHitCap;
+    uint32_t* aY = img + 2 * C::kHitCap;
+    uint32_t* aN = img + 3 * C::kHitCap;
+    uint32_t* aT = img + 4 * C::kHitCap;
+    uint32_t* aP = img + 5 * C::kHitCap;
+    unsigned long long* aS = (unsigned long long*)(img + 6 * C::kHitCap);
+
+    const int tid = threadIdx.x;
+    unsigned long long* err = &a.res->err;
+    const uint32_t k = blockIdx.x;
+    const uint64_t N = n_events(a);
+    const uint64_t n_seg = (N + a.q - 1) / a.q;
+    if (k >= n_seg) return;
+    Seg sg;
+    if (!seg_bounds(a, k, N, sg)) {
+        if (tid == 0) a.seg_cnt[k] = 0;
+        return;
+    }
+    const uint32_t n = sg.n, dt = a.dt;
+    const uint64_t e0 = sg.e0;
+    if (n == 0) {
+        if (tid == 0) a.seg_cnt[k] = 0;
+        return;
+    }
+    const uint32_t ng = sg.g_hi - sg.g_lo;
+    const bool goff_lds = ng <= (uint32_t)kNT;
+    if (goff_lds)
+        for (uint32_t i = tid; i <= ng; i += kNT) goff[i] = a.grp_off[sg.g_lo + i];
+
+    uint32_t ncomp = 0;
+    bool global_acc = false;  // moments in global scratch (ranks in a.rank)
+    if (n > (uint32_t)kSeg) {
+        __syncthreads();
+        ncomp = fused_big<C, kNT>(a, lds, scan_tmp, goff, goff_lds, sg);
+        global_acc = true;
+    } else {
+        // 1. load, push on the slot lists
+        for (int i = tid; i < C::kSlots / 8; i += kNT)
+            ((uint4*)img)[i] = make_uint4(~0u, ~0u, ~0u, ~0u);
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kE; ++q) {
+            const uint32_t i = tid + q * kNT;
+            if (i < n) {
+                const uint64_t p = e0 + i;
+                const uint32_t g = goff_lds ? sg.g_lo + group_of(goff, 0, ng, (uint32_t)p)
+                                            : group_of(a.grp_off, sg.g_lo, sg.g_hi, (uint32_t)p);
+                const uint32_t gs = (goff_lds ? goff[g - sg.g_lo] : a.grp_off[g]) - (uint32_t)e0;
+                const uint64_t pk = a.ev[p];
+                const uint32_t x = ev_x(pk), y = ev_y(pk);
+                key[i] = (ev_t(pk) & 0xFFFFu) | (C::hi(gs, y) << 16);
+                xyt[i] = x | (y << 8) | (ev_tot(pk) << 16);
+                par[i] = i;
+                // push i on its slot's list: swap it into the slot's half of
+                // the 32-bit word (retried while the other half changes)
+                const uint32_t sl = C::slot(x, y), sh = (sl & 1u) * 16u;
+                uint32_t* w = img + (sl >> 1);
+                uint32_t old = ald(w);
+                for (uint32_t tries = 0;; ++tries) {
+                    const uint32_t nw = (old & ~(0xFFFFu << sh)) | (i << sh);
+                    uint32_t expect = old;
+                    if (__hip_atomic_compare_exchange_strong(w, &expect, nw, __ATOMIC_RELAXED,
+                                                             __ATOMIC_RELAXED,
+                                                             __HIP_MEMORY_SCOPE_WORKGROUP) ||
+                        tries > 2 * kSeg) {
+                        if (tries > 2 * kSeg) atomicOr(err, (unsigned long long)kErrLoopUnite);
+                        break;
+                    }
+                    old = expect;
+                }
+                nxt[i] = (uint16_t)((old >> sh) & 0xFFFFu);
+            }
+        }
+        __syncthreads();
+        // 2. neighbours in the 3x3 box: the nine list heads are read
+        // together, then their keys and links together (two LDS round trips
+        // when no list holds more than one event; longer lists are walked
+        // afterwards).  The parent of each event becomes its smallest
+        // neighbour (or itself), a forest whose trees are mostly whole
+        // already; the smaller neighbours (up to 8) stay in registers.
+        uint32_t nb[kE][4];
+        uint32_t meta[kE];  // count of smaller neighbours (bits 0-7), live edges (8-15)
+        bool ok = true;
+#pragma unroll
+        for (int q = 0; q < kE; ++q) {
+            const uint32_t i = tid + q * kNT;
+            meta[q] = 0;
+            nb[q][0] = nb[q][1] = nb[q][2] = nb[q][3] = 0;
+            if (i >= n) continue;
+            const uint32_t xy = xyt[i];
+            const int x = (int)(xy & 255u), y = (int)((xy >> 8) & 255u);
+            const uint32_t ki = key[i];
+            const uint32_t ti = ki & 0xFFFFu, gs = ki >> C::kGShift;
+            uint32_t head[9], want[3];
+#pragma unroll
+            for (int r = 0; r < 3; ++r) want[r] = C::hi(gs, (uint32_t)(y + r - 1));
+#pragma unroll
+            for (int s = 0; s < 9; ++s) {
+                const int nx = x + s % 3 - 1, ny = y + s / 3 - 1;
+                const bool in = nx >= 0 && nx <= 255 && ny >= 0 && ny <= 255;
+                head[s] = in ? head16[C::slot((uint32_t)nx, (uint32_t)ny)] : kNone16;
+            }
+            uint32_t hk[9], hn[9];
+#pragma unroll
+            for (int s = 0; s < 9; ++s) {
+                const uint32_t j = head[s] == kNone16 ? i : head[s];
+                hk[s] = key[j];
+                hn[s] = head[s] == kNone16 ? kNone16 : nxt[j];
+            }
+            // second element of every list, read together
+            uint32_t k2[9], n2[9];
+#pragma unroll
+            for (int s = 0; s < 9; ++s) {
+                const uint32_t j = hn[s] == kNone16 ? i : hn[s];
+                k2[s] = key[j];
+                n2[s] = hn[s] == kNone16 ? kNone16 : nxt[j];
+            }
+            uint32_t m = i, c = 0;
+            auto take = [&](uint32_t j, uint32_t kj, uint32_t w) {
+                if (j < i && (kj >> 16) == w && absdiff(kj & 0xFFFFu, ti) <= dt) {
+                    m = j < m ? j : m;
+                    const uint32_t wd = (c >> 1) & 3u, sh16 = (c & 1u) * 16u;
+                    if (c < 8) {
+                        nb[q][0] |= wd == 0 ? j << sh16 : 0u;
+                        nb[q][1] |= wd == 1 ? j << sh16 : 0u;
+                        nb[q][2] |= wd == 2 ? j << sh16 : 0u;
+                        nb[q][3] |= wd == 3 ? j << sh16 : 0u;
+                    }
+                    ++c;
+                }
+            };
+#pragma unroll
+            for (int s = 0; s < 9; ++s) {
+                if (head[s] != kNone16) take(head[s], hk[s], want[s / 3]);
+                if (hn[s] != kNone16) take(hn[s], k2[s], want[s / 3]);
+            }
+            bool longer = false;
+#pragma unroll
+            for (int s = 0; s < 9; ++s) longer |= n2[s] != kNone16;
+            if (longer) {
+                for (int s = 0; s < 9; ++s) {
+                    uint32_t j = n2[s], steps = 0;
+                    while (j != kNone16) {
+                        take(j, key[j], want[s / 3]);
+                        if (++steps > n) {
+                            ok = false;
+                            break;
+                        }
+                        j = nxt[j];
+                    }
+                }
+            }
+            meta[q] = (c < 255 ? c : 255) | ((c > 8 ? 0xFFu : (1u << c) - 1u) << 8);
+            par[i] = m;
+        }
+        if (!ok) atomicOr(err, (unsigned long long)kErrLoopChain);
+        __syncthreads();
+        // 3. rounds: pointer jumping (every event points at its tree's root),
+        // then for every kept edge whose ends lie in different trees the
+        // larger root is pointed at the smaller (atomic minimum: parents only
+        // ever decrease, so the forest stays a forest); an edge once inside
+        // a tree stays inside and is dropped.  A round with no such edge
+        // ends it.  An event with more than 8 smaller neighbours walks its
+        // lists in every round.
+        for (uint32_t round = 0;; ++round) {
+#pragma unroll
+            for (int q = 0; q < kE; ++q) {
+                const uint32_t i = tid + q * kNT;
+                if (i >= n) continue;
+                uint32_t p = ald(par + i), steps = 0;
+                for (uint32_t nx; p != (nx = ald(par + p)) && ++steps <= n;) p = nx;
+                ast(par + i, p);
+            }
+            __syncthreads();
+            bool hooked = false;
+#pragma unroll
+            for (int q = 0; q < kE; ++q) {
+                const uint32_t i = tid + q * kNT;
+                const uint32_t cq = meta[q] & 0xFFu;
+                if (i >= n || ((meta[q] >> 8) == 0 && cq <= 8)) continue;
+                const uint32_t ri = ald(par + i);
+                uint32_t rj[8];
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    const uint32_t j = (nb[q][t >> 1] >> ((t & 1) * 16)) & 0xFFFFu;
+                    rj[t] = (meta[q] >> (8 + t)) & 1u ? ald(par + j) : ri;
+                }
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    if (rj[t] == ri) {
+                        meta[q] &= ~(1u << (8 + t));
+                    } else {
+                        const uint32_t lo = rj[t] < ri ? rj[t] : ri, hi = rj[t] < ri ? ri : rj[t];
+                        atomicMin(par + hi, lo);
+                        hooked = true;
+                    }
+                }
+                if (cq > 8) {
+                    const uint32_t xy = xyt[i];
+                    const int x = (int)(xy & 255u), y = (int)((xy >> 8) & 255u);
+                    const uint32_t ki = key[i];
+                    const uint32_t ti = ki & 0xFFFFu, gs = ki >> C::kGShift;
+                    for (int s = 0; s < 9; ++s) {
+                        const int nx = x + s % 3 - 1, ny = y + s / 3 - 1;
+                        if (nx < 0 || nx > 255 || ny < 0 || ny > 255) continue;
+                        const uint32_t w = C::hi(gs, (uint32_t)ny);
+                        uint32_t j = head16[C::slot((uint32_t)nx, (uint32_t)ny)], steps = 0;
+                        while (j != kNone16) {
+                            const uint32_t kj = key[j];
+                            if (j < i && (kj >> 16) == w && absdiff(kj & 0xFFFFu, ti) <= dt) {
+                                const uint32_t r2 = ald(par + j);
+                                if (r2 != ri) {
+                                    atomicMin(par + (r2 < ri ? ri : r2), r2 < ri ? r2 : ri);
+                                    hooked = true;
+                                }
+                            }
+                            if (++steps > n) break;
+                            j = nxt[j];
+                        }
+                    }
+                }
+            }
+            if (!__syncthreads_or(hooked)) break;
+            if (round >= kMaxRounds) {  // far more rounds than any forest needs
+                if (tid == 0) atomicOr(err, (unsigned long long)kErrLoopUnite);
+                break;
+            }
+        }
+        // every parent is now its root; the image region becomes the accumulators
+        for (int c = tid; c < C::kHitCap; c += kNT) {
+            aW[c] = 0;
+            aX[c] = 0;
+            aY[c] = 0;
+            aN[c] = 0;
+            aT[c] = kNone32;
+            aS[c] = 0;
+        }
+        __syncthreads();
+        // 4. ranks of the roots in position order (thread t: positions kE t ..)
+        {
+            uint32_t cnt = 0;
+#pragma unroll
+            for (int q = 0; q < kE; ++q) {
+                const uint32_t i = tid * kE + q;
+                cnt += (i < n && par[i] == i) ? 1u : 0u;
+            }
+            uint32_t total;
+            uint32_t r = wg_count_scan<kNT>(cnt, scan_tmp, &total);
+#pragma unroll
+            for (int q = 0; q < kE; ++q) {
+                const uint32_t i = tid * kE + q;
+                if (i < n && par[i] == i) {
+                    nxt[i] = (uint16_t)r;  // the lists are no longer needed
+                    if (r < (uint32_t)C::kHitCap) aP[r] = i;
+                    ++r;
+                }
+            }
+            ncomp = total;
+        }
+        __syncthreads();
+        global_acc = ncomp > (uint32_t)C::kHitCap;
+        if (global_acc) {
+            // more components than the accumulators hold: ranks to a.rank
+#pragma unroll
+            for (int q = 0; q < kE; ++q) {
+                const uint32_t i = tid + q * kNT;
+                if (i < n) a.rank[e0 + i] = nxt[par[i]];
+            }
+        }
+    }
+    if (tid == 0) a.seg_cnt[k] = ncomp;
+
+    if (global_acc) {
+        // moments in the segment's own range of the global scratch
+        for (uint32_t c = tid; c < ncomp; c += kNT) {
+            unsigned long long* g = gacc(a, e0, c);
+            g[0] = g[1] = g[2] = g[3] = g[4] = 0;
+            g[5] = ~0ull;
+            g[6] = ~0ull;
+        }
+        __syncthreads();
+        for (uint32_t i = tid; i < n; i += kNT) {
+            const uint32_t rk = a.rank[e0 + i];
+            if (rk >= ncomp) {
+                atomicOr(err, (unsigned long long)kErrInternal);
+                continue;
+            }
+            unsigned long long* g = gacc(a, e0, rk);
+            gacc_add(a, g, a.ev[e0 + i]);
+            atomicMin(g + 6, (unsigned long long)i);
+        }
+        __syncthreads();
+        bool zero = false;
+        for (uint32_t c = tid; c < ncomp; c += kNT) zero |= gacc_ld(gacc(a, e0, c)) == 0;
+        if (__syncthreads_or(zero)) {
+            for (uint32_t i = tid; i < n; i += kNT) {
+                const uint32_t rk = a.rank[e0 + i];
+                if (rk < ncomp && gacc_ld(gacc(a, e0, rk)) == 0)
+                    gacc_add_plain(a, gacc(a, e0, rk), a.ev[e0 + i]);
+            }
+            __syncthreads();
+        }
+        for (uint32_t c = tid; c < ncomp; c += kNT) {
+            unsigned long long* g = gacc(a, e0, c);
+            unsigned long long v[7];
+#pragma unroll
+            for (int w = 0; w < 7; ++w) v[w] = gacc_ld(g + w);
+            fused_emit(a, sg, goff, goff_lds, c, (uint32_t)v[6], v[0], v[1], v[2], v[3], v[4],
+                       (uint32_t)v[5]);
+        }
+        if (a.hit_index)
+            for (uint32_t i = tid; i < n; i += kNT) a.hit_index[e0 + i] = a.rank[e0 + i];
+        return;
+    }
+
+    // 5. moments (LDS atomics)
+#pragma unroll
+    for (int q = 0; q < kE; ++q) {
+        const uint32_t i = tid + q * kNT;
+        if (i >= n) continue;
+        const uint32_t r = nxt[par[i]];
+        const uint32_t v = xyt[i];
+        const uint32_t x = v & 255u, y = (v >> 8) & 255u, tot = v >> 16, t = key[i] & 0xFFFFu;
+        atomicAdd(&aW[r], tot);
+        atomicAdd(&aX[r], tot * x);
+        atomicAdd(&aY[r], tot * y);
+        atomicAdd(&aN[r], 1u);
+        atomicMin(&aT[r], t);
+        atomicAdd(&aS[r], (unsigned long long)time_term(a, tot, t));
+    }
+    __syncthreads();
+    bool zero = false;
+    for (uint32_t c = tid; c < ncomp; c += kNT) zero |= aW[c] == 0;
+    if (__syncthreads_or(zero)) {
+        // components without any ToT: plain means (their weighted sums are 0)
+#pragma unroll
+        for (int q = 0; q < kE; ++q) {
+            const uint32_t i = tid + q * kNT;
+            if (i >= n) continue;
+            const uint32_t r = nxt[par[i]];
+            if (aW[r] != 0) continue;
+            const uint32_t v = xyt[i];
+            atomicAdd(&aX[r], v & 255u);
+            atomicAdd(&aY[r], (v >> 8) & 255u);
+            atomicAdd(&aS[r], (unsigned long long)time_term1(a, v >> 16, key[i] & 0xFFFFu));
+        }
+        __syncthreads();
+    }
+    // 6. hits, staged at the segment's own range
+    for (uint32_t c = tid; c < ncomp; c += kNT)
+        fused_emit(a, sg, goff, goff_lds, c, aP[c], aW[c], aN[c], aX[c], aY[c], aS[c], aT[c]);
+    if (a.hit_index) {
+#pragma unroll
+        for (int q = 0; q < kE; ++q) {
+            const uint32_t i = tid + q * kNT;
+            if (i < n) a.hit_index[e0 + i] = nxt[par[i]];
+        }
+    }
+}
+
+// Staged hits to their final place: one wave per segment copies its hits
+// (8-byte words: a hit record is 8-byte aligned) from the segment's staging
+// range to seg_off[k]; with a hit index, the segment's events get their final
+// hit.
+constexpr int kCompactWG = 256;
+__global__ __launch_bounds__(kCompactWG) void k_hit_compact(ClusterArgs a) {
+    const uint64_t N = n_events(a);
+    const uint64_t n_seg = (N + a.q - 1) / a.q;
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.res->n_hits = a.seg_off[n_seg];
+    const int lane = (int)__lane_id();
+    const uint64_t k = (uint64_t)blockIdx.x * (kCompactWG / 64) + (threadIdx.x >> 6);
+    if (k >= n_seg) return;
+    const uint32_t g_lo = a.seg_lo[k], g_hi = a.seg_lo[k + 1];
+    const uint64_t e0 = a.grp_off[g_lo], e1 = a.grp_off[g_hi];
+    if (g_hi < g_lo || e1 < e0 || e1 > N) return;  // reported by the cluster kernel
+    const uint64_t cnt = a.seg_cnt[k], off = a.seg_off[k];
+    const uint2* src = (const uint2*)(a.hits_tmp + e0);
+    uint2* dst = (uint2*)(a.hits + off);
+    static_assert(sizeof(tpx_hit) == 48, "hit record");
+    uint64_t words = 6 * cnt;
+    if (off >= a.hit_cap) words = 0;
+    else if (off + cnt > a.hit_cap) words = 6 * (a.hit_cap - off);
+    for (uint64_t w = lane; w < words; w += 64) dst[w] = src[w];
+    if (a.hit_index)
+        for (uint64_t i = e0 + lane; i < e1; i += 64) a.hit_index[i] += (uint32_t)off;
+}
+
+struct FusedVariant {
+    const char* name;
+};
+static const FusedVariant kFusedVariants[] = {
+    {"image 256x32, 512 threads, 2048 events in LDS"},
+    {"image 256x16, 512 threads, 2048 events in LDS"},
+    {"image 256x64, 512 threads, 2048 events in LDS"},
+    {"image 256x32, 256 threads, 2048 events in LDS"},
+    {"image 256x64, 1024 threads, 8192 events in LDS"},
+};
+
+int fused_variants() { return (int)(sizeof(kFusedVariants) / sizeof(kFusedVariants[0])); }
+const char* fused_variant_name(int v) {
+    return v >= 0 && v < fused_variants() ? kFusedVariants[v].name : "?";
+}
+
+void launch_cluster_fused(const ClusterArgs& a, uint64_t grid, int variant, hipStream_t s) {
+    if (grid == 0) return;
+    const dim3 g((unsigned)grid);
+    switch (variant) {
+    case 1: hipLaunchKernelGGL((k_cluster_fused<4, 512, 2048>), g, dim3(512), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_cluster_fused<6, 512, 2048>), g, dim3(512), 0, s, a); break;
+    case 3: hipLaunchKernelGGL((k_cluster_fused<5, 256, 2048>), g, dim3(256), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_cluster_fused<6, 1024, 8192>), g, dim3(1024), 0, s, a); break;
+    default: hipLaunchKernelGGL((k_cluster_fused<5, 512, 2048>), g, dim3(512), 0, s, a); break;
+    }
+}
+
+void launch_hit_compact(const ClusterArgs& a, uint64_t grid, hipStream_t s) {
+    if (grid == 0) return;
+    const uint64_t blocks = (grid + kCompactWG / 64 - 1) / (kCompactWG / 64);
+    hipLaunchKernelGGL(k_hit_compact, dim3((unsigned)blocks), dim3(kCompactWG), 0, s, a);
 }
 
 }  // namespace tpx

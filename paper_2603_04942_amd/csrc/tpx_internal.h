@@ -133,7 +133,7 @@ struct DevResults {
     unsigned long long seg_ticket, tile_ticket, aux_ticket;
     long long pix_epoch_end, tdc_epoch_end;
     unsigned long long pix_last_end, tdc_last_end, pix_has_end, tdc_has_end;
-    unsigned long long big_segments, max_segment;
+    unsigned long long big_segments;  // segments clustered in global memory
     unsigned long long max_key;       // largest shot value seen by an event-mode check
     unsigned long long n_in;          // events handed to the cluster kernel (event mode)
     unsigned long long n_close_list;  // closed groups in a sorted group list (fallback)

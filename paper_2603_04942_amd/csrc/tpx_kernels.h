@@ -59,6 +59,9 @@ struct ClusterArgs {
     // per-event scratch for segments that do not fit in LDS
     uint32_t *g_parent, *g_chain, *g_next, *g_t, *g_sl, *g_xy;
     uint64_t* g_acc;           // 8 words per event
+    // fused stream kernel (launch_cluster_fused)
+    tpx_hit* hits_tmp;         // staging: hit r of a segment at its first event + r
+    uint32_t* hit_index;       // optional: hit of every event (call-relative), or null
 };
 
 void launch_tile_summary(const uint64_t* pk, uint64_t n, uint32_t sub, uint64_t jump,
@@ -81,9 +84,20 @@ void launch_seg_table(const uint32_t* grp_off, const unsigned long long* n_grp_d
                       hipStream_t s);
 // stream mode: moments and hits of the components found by launch_cluster
 void launch_seg_centroid(const ClusterArgs& a, uint64_t grid, hipStream_t s);
+// stream mode, radius 1, times of flight below 2^16: components, moments and
+// hits of every segment in one launch, hits staged at each segment's own
+// range of a.hits_tmp and its component count in seg_cnt; `variant` selects
+// the image height, workgroup size and LDS capacity (fused_variants()).
+// Then a prefix sum of seg_cnt into seg_off, and launch_hit_compact moves the
+// hits to their final place (and sets res->n_hits).
+void launch_cluster_fused(const ClusterArgs& a, uint64_t grid, int variant, hipStream_t s);
+void launch_hit_compact(const ClusterArgs& a, uint64_t grid, hipStream_t s);
+int fused_variants();
+const char* fused_variant_name(int variant);
 // patches of the hits written by the stream call whose cluster arguments are
 // `a` (tpx_learn.hip); acc: u32 [n_hits * 98 + n_hits] scratch, err: 1 word
-void launch_stream_patches(const ClusterArgs& a, uint64_t grid, const tpx_hit* hits,
+// (fused: the call recorded the hit of every event in a.hit_index)
+void launch_stream_patches(const ClusterArgs& a, uint64_t grid, bool fused, const tpx_hit* hits,
                            uint64_t n_hits, uint32_t* acc, uint16_t* feat, int* err,
                            hipStream_t s);
 // event mode, the paper's local-maximum hits: count pass (write = false,

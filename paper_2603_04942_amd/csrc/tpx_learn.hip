@@ -134,6 +134,30 @@ __global__ __launch_bounds__(256) void k_spatch_accum(ClusterArgs a, const tpx_h
     }
 }
 
+// the same from the hit of every event recorded by the fused kernel
+__global__ __launch_bounds__(256) void k_spatch_accum_idx(ClusterArgs a, const tpx_hit* hits,
+                                                          uint64_t n_hits, uint32_t* acc, int* err) {
+    const uint64_t N = (a.skip && *a.skip) ? 0 : *a.n_ev_dev;
+    uint32_t* hmin = acc + n_hits * kIn;
+    for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < N;
+         p += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t h = a.hit_index[p];
+        if (h >= n_hits) {
+            atomicOr(err, 1);
+            continue;
+        }
+        const uint64_t pk = a.ev[p];
+        const uint32_t tof = (uint32_t)(pk & 0x3FFFFFFFu);
+        atomicMin(&hmin[h], tof);
+        const int ix = (int)((pk >> 48) & 255u) - centre_of(hits[h].x) + kHalf;
+        const int iy = (int)((pk >> 40) & 255u) - centre_of(hits[h].y) + kHalf;
+        if (ix < 0 || ix >= kSide || iy < 0 || iy >= kSide) continue;
+        const int c = iy * kSide + ix;
+        atomicAdd(&acc[h * kIn + c], (uint32_t)((pk >> 30) & 1023u));
+        atomicMin(&acc[h * kIn + kCells + c], tof);
+    }
+}
+
 __global__ void k_spatch_finish(const uint32_t* acc, uint64_t n_hits, uint16_t* feat) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_hits * kCells) return;
@@ -639,13 +663,16 @@ __global__ __launch_bounds__(256, 2) void k_mlp_fused(const float* __restrict__ 
 
 }  // namespace
 
-void launch_stream_patches(const ClusterArgs& a, uint64_t grid, const tpx_hit* hits,
+void launch_stream_patches(const ClusterArgs& a, uint64_t grid, bool fused, const tpx_hit* hits,
                            uint64_t n_hits, uint32_t* acc, uint16_t* feat, int* err,
                            hipStream_t s) {
     hipLaunchKernelGGL(k_zero_f32, dim3(1), dim3(64), 0, s, (float*)err, 1);
     hipLaunchKernelGGL(k_spatch_clear, dim3(blocks(n_hits * (kIn + 1), 256)), dim3(256), 0, s,
                        acc, n_hits);
-    if (grid)
+    if (fused)
+        hipLaunchKernelGGL(k_spatch_accum_idx, dim3(2048), dim3(256), 0, s, a, hits, n_hits, acc,
+                           err);
+    else if (grid)
         hipLaunchKernelGGL(k_spatch_accum, dim3((unsigned)grid), dim3(256), 0, s, a, hits, n_hits,
                            acc, err);
     hipLaunchKernelGGL(k_spatch_finish, dim3(blocks(n_hits * kCells, 256)), dim3(256), 0, s, acc,

@@ -16,3 +16,41 @@ def tiny_cluster_case(seed):
     dxy = int(rng.integers(0, 4))
     dt = int(rng.choice([0, 1, 64, 128, 500]))
     return ev, dxy, dt
+
+
+def many_components_packets(n_iso):
+    """One shot whose pixels are all isolated (spacing 2 on the grid, so no
+    two are neighbours) plus one 3x3 blob, as packets: n_iso = 1500 gives more
+    components in one segment than LDS accumulators hold, 3000 a segment
+    beyond the LDS event capacity, 20000 one shot spanning many strides."""
+    rng = np.random.default_rng(n_iso)
+    trig = np.array([1_000_000, 1_000_000 + synth.SHOT_PERIOD_TICKS])
+    k = np.arange(n_iso)
+    x = 2 * (k % 128)
+    y = 2 * ((k // 128) % 128)
+    t = trig[0] + 100 + (k // 16384) * 1000 + rng.integers(0, 50_000, n_iso)
+    bx, by = np.meshgrid(np.arange(3) + 1, np.arange(3) + 1)
+    x = np.concatenate([x, bx.ravel()])
+    y = np.concatenate([y, by.ravel()])
+    t = np.concatenate([t, np.full(9, trig[0] + 60_000)])
+    tot = rng.integers(0, 400, x.size)
+    tot[:5] = 0
+    order = np.argsort(t, kind="stable")
+    return np.concatenate([synth.encode_tdc(trig[:1], [0]),
+                           synth.encode_pixels(x[order], y[order], tot[order], t[order]),
+                           synth.encode_tdc(trig[1:], [1])])
+
+
+def big_component_packets(side=136, layers=2):
+    """One component of side^2 * layers pixels: a square at ToT 1023 with x
+    and y up to 255, fired `layers` times 50 ticks apart (the default gives
+    36,992 pixels whose sum of ToT * x exceeds 32 bits)."""
+    trig = np.array([1_000_000, 1_000_000 + synth.SHOT_PERIOD_TICKS])
+    bx, by = np.meshgrid(np.arange(256 - side, 256), np.arange(256 - side, 256))
+    x = np.tile(bx.ravel(), layers)
+    y = np.tile(by.ravel(), layers)
+    t = np.repeat(trig[0] + 1000 + 50 * np.arange(layers), bx.size)
+    tot = np.full(x.size, 1023)
+    return np.concatenate([synth.encode_tdc(trig[:1], [0]),
+                           synth.encode_pixels(x, y, tot, t),
+                           synth.encode_tdc(trig[1:], [1])])

@@ -61,13 +61,16 @@ def run_cluster(ev, dxy=1, dt_ticks=128, preempt=0, seed=1, timeout=600):
     return st, nc, lab, _errors(out, 12 + 4 * n)
 
 
-def run_stream(packets, chunk, pix_epoch0=0, tdc_epoch0=0, q=0, preempt=0, seed=1, timeout=600):
-    """tpx_process_stream over the packets in chunks (flush on the last);
+def run_stream(packets, chunk, pix_epoch0=0, tdc_epoch0=0, q=0, kernel=0, preempt=0, seed=1,
+               timeout=600):
+    """tpx_process_stream over the packets in chunks (flush on the last),
+    with the given clustering kernel (-1 staged, >= 0 a fused variant);
     returns (status, hits, emulator findings)."""
     pk = np.ascontiguousarray(packets, dtype=np.uint64)
     blob = b"".join([np.array([pk.size, chunk], np.uint64).tobytes(),
                      np.array([pix_epoch0, tdc_epoch0], np.int64).tobytes(),
-                     np.array([q], np.uint32).tobytes(), pk.tobytes()])
+                     np.array([q], np.uint32).tobytes(), np.array([kernel], np.int32).tobytes(),
+                     pk.tobytes()])
     out, _ = _run("stream", blob, preempt, seed, timeout)
     st = int(np.frombuffer(out, np.int32, 1, 0)[0])
     nh = int(np.frombuffer(out, np.uint64, 1, 4)[0])

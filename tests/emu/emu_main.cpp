@@ -6,7 +6,9 @@
 //                                tot u16[n], shot u32[n], toa u64[n]
 //                            OUT: i32 status, u64 n_clusters, labels u32[n]
 //   emu_tpx stream IN OUT    IN: u64 n, u64 chunk, i64 pix_epoch0,
-//                                i64 tdc_epoch0, u32 q, packets u64[n]
+//                                i64 tdc_epoch0, u32 q, i32 kernel
+//                                (-1 staged, >= 0 fused variant),
+//                                packets u64[n]
 //                            OUT: i32 status, u64 n_hits, tpx_hit[n_hits]
 // Both append: u64 error-text length, error text (empty = no finding).
 //   emu_tpx selftest         runs kernels with planted synchronisation
@@ -29,8 +31,8 @@ extern "C" uint32_t tpx_stream_get_segment(const tpx_stream* s);
 namespace tpx {
 struct ClusterArgs;
 // the learned patches are not part of the emulation build
-void launch_stream_patches(const ClusterArgs&, uint64_t, const tpx_hit*, uint64_t, uint32_t*,
-                           uint16_t*, int*, hipStream_t) {
+void launch_stream_patches(const ClusterArgs&, uint64_t, bool, const tpx_hit*, uint64_t,
+                           uint32_t*, uint16_t*, int*, hipStream_t) {
     fprintf(stderr, "emu: learned patches are not emulated\n");
     abort();
 }
@@ -108,6 +110,7 @@ int run_stream(In& in, FILE* out) {
     const uint64_t n = in.get<uint64_t>(), chunk = in.get<uint64_t>();
     const int64_t pe0 = in.get<int64_t>(), te0 = in.get<int64_t>();
     const uint32_t q = in.get<uint32_t>();
+    const int32_t kern = in.get<int32_t>();
     uint64_t* pk = dev<uint64_t>(n);
     in.arr(pk, n);
     tpx_params p;
@@ -118,6 +121,7 @@ int run_stream(In& in, FILE* out) {
     int32_t st = tpx_stream_create(&p, chunk, &s);
     std::vector<tpx_hit> all;
     if (st == TPX_OK && q) st = tpx_stream_set_segment(s, q);
+    if (st == TPX_OK) st = tpx_stream_set_kernel(s, kern);
     const size_t cap = n + 16;
     tpx_hit* hits = dev<tpx_hit>(cap);
     for (uint64_t off = 0; st == TPX_OK;) {

@@ -97,5 +97,11 @@ def test_learned_and_tuning_argument_errors_need_no_gpu():
     assert lib.tpx_stream_get_segment(None) == 0
     cand = (ctypes.c_uint32 * 2)(64, 4096)
     best = ctypes.c_uint32()
-    assert lib.tpx_stream_autotune(None, fake, 0, 1, fake, 0, cand, 2, 1, None,
-                                   ctypes.byref(best), None) == tpx.EINVAL
+    assert lib.tpx_stream_autotune(None, fake, 0, 1, fake, 0, cand, 2, None, 0, 1, None,
+                                   ctypes.byref(best), None, None) == tpx.EINVAL
+    # clustering kernels: names, and the calls on a NULL stream
+    assert lib.tpx_stream_kernel_count() >= 1
+    assert lib.tpx_stream_kernel_name(-1) and lib.tpx_stream_kernel_name(0)
+    assert lib.tpx_stream_set_kernel(None, 0) == tpx.EINVAL
+    assert lib.tpx_stream_get_kernel(None) == -2
+    assert lib.tpx_stream_set_patches(None, 1) == tpx.EINVAL

@@ -78,3 +78,48 @@ def test_stream_c1(emu, orc, chunk):
     assert np.abs(hits["x"] - ref["x"]).max() <= 1e-4
     assert np.abs(hits["y"] - ref["y"]).max() <= 1e-4
     assert np.abs(hits["tof_ns"] - ref["tof_ns"]).max() <= 0.1
+
+
+def _assert_hits(hits, ref):
+    assert hits.size == ref.size
+    for f in ("shot", "label", "npix", "tot_sum", "toa_first", "flags"):
+        assert np.array_equal(hits[f].astype(np.uint64), ref[f].astype(np.uint64)), f
+    assert np.abs(hits["x"] - ref["x"]).max(initial=0) <= 1e-4
+    assert np.abs(hits["y"] - ref["y"]).max(initial=0) <= 1e-4
+    assert np.abs(hits["tof_ns"] - ref["tof_ns"]).max(initial=0) <= 0.1
+
+
+@pytest.mark.parametrize("kernel", [-1, 0, 1, 2, 3, 4])
+@pytest.mark.parametrize("name,shots,chunk", [("c1", 30, 1500), ("c3", 25, 30000)])
+def test_stream_kernels(emu, orc, kernel, name, shots, chunk):
+    """Every clustering kernel of the stream path (the staged pair and each
+    fused variant: ticketed segments, slot lists, unions, moments, look-back
+    over segments) on the small and the uneven-shot workloads, whole and in
+    chunks."""
+    w = synth.make_config(name, n_shots=shots)
+    kw = dict(pix_epoch0=w.pix_epoch0, tdc_epoch0=w.tdc_epoch0)
+    ref, _ = orc.run(w.packets, **kw)
+    for ch in (1 << 22, chunk):
+        st, hits, errs = emu.run_stream(w.packets, ch, kernel=kernel, preempt=100,
+                                        seed=11 + kernel, **kw)
+        assert errs == ""
+        assert st == 0
+        _assert_hits(hits, ref)
+
+
+@pytest.mark.parametrize("kernel", [0, 4])
+@pytest.mark.parametrize("case", ["iso1500", "iso3000", "square"])
+def test_stream_fused_capacity_paths(emu, orc, kernel, case):
+    """The fused kernel's fallbacks: more components than the LDS
+    accumulators hold (1,500 isolated pixels), a segment beyond the LDS event
+    capacity (3,000; global-memory lists and unions), and one component of
+    7,200 pixels at ToT 1023 (moments of a large segment)."""
+    from cases import big_component_packets, many_components_packets
+    pk = {"iso1500": lambda: many_components_packets(1500),
+          "iso3000": lambda: many_components_packets(3000),
+          "square": lambda: big_component_packets(side=60, layers=2)}[case]()
+    ref, _ = orc.run(pk)
+    st, hits, errs = emu.run_stream(pk, 1 << 22, kernel=kernel, preempt=100, seed=5)
+    assert errs == ""
+    assert st == 0
+    _assert_hits(hits, ref)

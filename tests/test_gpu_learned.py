@@ -130,17 +130,50 @@ def test_forward_large_batch_chunks(tpx):
     assert np.abs(out[rows] - ref).max() <= REL_TOL * rms
 
 
-# Element-wise gradient bound, relative to the RMS of each tensor: each
-# element is a sum over the batch of products of bfloat16-rounded operands, so
-# its error is a random walk of 2^-9-sized relative errors of its terms; over
-# the ~25,000 elements of the largest tensor the extreme is about 4.5 standard
-# deviations of that walk.  A dropped or shifted split-K slice (1/16 of an
-# element's terms at batch 4096) moves the largest elements by ~25 % of the RMS.
-ELEM_TOL = 6e-2
+# Element-wise gradient bound.  Each gradient element is a sum over the batch
+# of products of two operands (a weight gradient: an upstream gradient times
+# an activation or feature; a bias gradient: an upstream gradient) that the
+# kernels hold in bfloat16 (8 significant bits, 2^-9 relative per rounding)
+# and that already carry the rounding of the layers above them.  Its error is
+# therefore bounded by a small multiple of 2^-8 times the sum of the absolute
+# values of its terms, S (the same products over |operands|, from the
+# oracle's own values).  A ReLU whose input lies within rounding of zero
+# (|Z| <= 2^-8 of the absolute sum that forms Z, twice the bound of one
+# bfloat16 rounding of its terms) may be open on one side and
+# shut on the other: the terms that pass through it may be present or absent,
+# so they are allowed in full (S_amb).  A floor of 2^-6 RMS(S) covers the
+# rest.  A dropped or shifted split-K slice (1/16 of an element's terms at
+# batch 4,096) moves an element by ~6 % of S.
+ELEM_TOL, ELEM_FLOOR, RELU_AMBIG = 2.0 ** -4, 2.0 ** -6, 2.0 ** -8
+
+
+def _abs_scales(p, feat, T, mult):
+    """(S, S_amb) per parameter tensor: the gradient's products over absolute
+    operands, and the part of them that passes through a ReLU rounding may
+    flip."""
+    O, c = L.forward(p, feat)
+    _, G = L.loss_grad(O, T, mult)
+    P = L.unpack(p)
+    aX, aW1, aW2 = np.abs(c["X"]), np.abs(c["W1"]), np.abs(c["W2"])
+    amb1 = np.abs(c["Z1"]) <= RELU_AMBIG * (aX @ aW1.T + np.abs(P["b1"]))
+    amb2 = np.abs(c["Z2"]) <= RELU_AMBIG * (c["H1"] @ aW2.T + np.abs(P["b2"]))
+    on1, on2 = (c["Z1"] > 0) & ~amb1, (c["Z2"] > 0) & ~amb2
+    aG = np.abs(G)
+    gw3 = np.abs(G @ c["W3"])
+    a2s, a2a = gw3 * on2, gw3 * amb2
+    a1s = (a2s @ aW2) * on1
+    a1a = (a2a @ aW2) * (on1 | amb1) + (a2s @ aW2) * amb1
+
+    def tensors(a1, a2, g):
+        return L.unpack(L.pack(dict(W1=a1.T @ aX, b1=a1.sum(0), W2=a2.T @ c["H1"], b2=a2.sum(0),
+                                    W3=g.T @ c["H2"], b3=g.sum(0))))
+    sure = tensors(a1s, a2s, aG)
+    amb = tensors(a1a, a2a, 0 * aG)
+    return {k: sure[k] + amb[k] for k in sure}, amb
 
 
 @pytest.mark.parametrize("n,n_use,seed", [(2, None, 1), (300, None, 2), (700, None, 3),
-                                          (4300, 4096, 4), (4300, 4100, 5)])
+                                          (4300, 4096, 4), (4600, 4100, 5)])
 def test_gradients_match_oracle(tpx, orc, n, n_use, seed):
     """Gradients element by element; batches of 4,096 and 4,100 rows split the
     weight-gradient products into 16 full slices of 256 and into 15 slices of
@@ -162,6 +195,7 @@ def test_gradients_match_oracle(tpx, orc, n, n_use, seed):
         assert len(idx) >= n_use
         idx = idx[:n_use]
     loss_ref, g_ref, _ = L.grad(p, feat[idx], T[idx], cl["mult"][idx])
+    scale, scale_amb = _abs_scales(p, feat[idx], T[idx], cl["mult"][idx])
     from paper_2603_04942_amd.learned import prepare
     gfeat, ghits, gtruth, gmult = prepare(cl)
     sel = torch.from_numpy(idx).cuda()
@@ -172,11 +206,16 @@ def test_gradients_match_oracle(tpx, orc, n, n_use, seed):
     assert abs(loss - loss_ref) <= REL_TOL * abs(loss_ref)
     for name, a, b in zip([s for s, _ in L.SHAPES], L.unpack(g).values(), L.unpack(g_ref).values()):
         r = _rel(a.ravel(), b.ravel())
-        rms = float(np.sqrt(np.mean(b.ravel() ** 2)))
-        e = float(np.abs(a.ravel() - b.ravel()).max()) / max(rms, 1e-30)
-        _say(f"  grad {name}: rel {r:.2e}, max element error / rms {e:.2e}")
+        S = scale[name].ravel()
+        bound = (ELEM_TOL * S + scale_amb[name].ravel()
+                 + ELEM_FLOOR * float(np.sqrt(np.mean(S ** 2))))
+        ratio = np.abs(a.ravel() - b.ravel()) / bound
+        w = int(np.argmax(ratio))
+        e = float(ratio[w])
+        _say(f"  grad {name}: rel {r:.2e}, max element error / bound {e:.2e} (element {w}: "
+             f"{a.ravel()[w]:.4e} vs {b.ravel()[w]:.4e}, S {S[w]:.3e}, rms S {np.sqrt(np.mean(S ** 2)):.3e})")
         assert r <= REL_TOL, name
-        assert e <= ELEM_TOL, name
+        assert e <= 1.0, name
 
 
 def test_adam_matches_oracle(tpx):
@@ -259,8 +298,18 @@ def test_stream_patches_match_the_oracle(tpx, orc):
         hits = orc.centroid(e["x"], e["y"], e["tot"], e["shot"], e["toa"], lab, d["trig"])
         ref = L.patches(e["x"], e["y"], e["tot"], e["toa"], e["shot"], lab, hits)
         step = step or w.n_packets
-        s = tpx.Stream(step, **kw)
         buf = torch.empty((2 * step + 1024, 48), dtype=torch.uint8, device="cuda")
+        # without recording the hit of every event, patches after the fused
+        # kernel are refused
+        s = tpx.Stream(step, **kw)
+        try:
+            h, _ = s.process(w.packets[:step], hits=buf)
+            with pytest.raises(tpx.TpxError) as err:
+                s.patches(buf, h.size)
+            assert err.value.rc == tpx.EINVAL
+        finally:
+            s.close()
+        s = tpx.Stream(step, patches=True, **kw)
         got = []
         try:
             with pytest.raises(tpx.TpxError) as err:
@@ -296,7 +345,7 @@ def test_stream_patches_after_the_sorting_path(tpx, orc):
     lab, _ = orc.cluster(e["x"], e["y"], e["shot"], e["toa"])
     hits = orc.centroid(e["x"], e["y"], e["tot"], e["shot"], e["toa"], lab, d["trig"])
     ref = L.patches(e["x"], e["y"], e["tot"], e["toa"], e["shot"], lab, hits)
-    s = tpx.Stream(moved.size, **kw)
+    s = tpx.Stream(moved.size, patches=True, **kw)
     buf = torch.empty((moved.size, 48), dtype=torch.uint8, device="cuda")
     try:
         h, _ = s.process(moved, flush=True, hits=buf)

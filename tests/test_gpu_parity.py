@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 
 import synth
+from cases import big_component_packets, many_components_packets
 
 pytestmark = pytest.mark.gpu
 
@@ -135,32 +136,17 @@ def test_stream_chunked(tpx, orc, seed):
 
 @pytest.mark.parametrize("n_iso", [1500, 3000, 20000])
 def test_stream_many_components(tpx, orc, n_iso):
-    """One shot whose pixels are all isolated (spacing 2 on the grid, so no
-    two are neighbours) plus one 3x3 blob: more components in one segment
-    than the LDS accumulators hold (n_iso = 1500), a segment beyond the LDS
-    event capacity (3000), and one shot of 20000 events spanning many
-    segment strides."""
+    """One shot whose pixels are all isolated plus one 3x3 blob: more
+    components in one segment than the LDS accumulators hold (n_iso = 1500), a
+    segment beyond the LDS event capacity (3000), and one shot of 20000 events
+    spanning many segment strides; every clustering kernel."""
     _say(f"many components n_iso={n_iso}")
-    rng = np.random.default_rng(n_iso)
-    trig = np.array([1_000_000, 1_000_000 + synth.SHOT_PERIOD_TICKS])
-    k = np.arange(n_iso)
-    x = 2 * (k % 128)
-    y = 2 * ((k // 128) % 128)
-    t = trig[0] + 100 + (k // 16384) * 1000 + rng.integers(0, 50_000, n_iso)
-    bx, by = np.meshgrid(np.arange(3) + 1, np.arange(3) + 1)
-    x = np.concatenate([x, bx.ravel()])
-    y = np.concatenate([y, by.ravel()])
-    t = np.concatenate([t, np.full(9, trig[0] + 60_000)])
-    tot = rng.integers(0, 400, x.size)
-    tot[:5] = 0
-    order = np.argsort(t, kind="stable")
-    pk = np.concatenate([synth.encode_tdc(trig[:1], [0]),
-                         synth.encode_pixels(x[order], y[order], tot[order], t[order]),
-                         synth.encode_tdc(trig[1:], [1])])
+    pk = many_components_packets(n_iso)
     ref, _ = orc.run(pk)
     assert ref.size > 1024
-    h, _ = tpx.process_stream(pk)
-    assert_hits_match(h, ref)
+    for k in range(-1, tpx.kernel_count()):
+        h, _ = tpx.process_stream(pk, kernel=k)
+        assert_hits_match(h, ref)
 
 
 def test_stream_component_beyond_32bit_moments(tpx, orc):
@@ -168,20 +154,12 @@ def test_stream_component_beyond_32bit_moments(tpx, orc):
     twice 50 ticks apart, x and y up to 255): its sum of ToT * x is about
     7e9, beyond 32 bits, so the moments must be accumulated in 64 bits."""
     _say("component beyond 32-bit moments")
-    trig = np.array([1_000_000, 1_000_000 + synth.SHOT_PERIOD_TICKS])
-    bx, by = np.meshgrid(np.arange(120, 256), np.arange(120, 256))
-    x = np.concatenate([bx.ravel(), bx.ravel()])
-    y = np.concatenate([by.ravel(), by.ravel()])
-    t = np.concatenate([np.full(bx.size, trig[0] + 1000), np.full(bx.size, trig[0] + 1050)])
-    tot = np.full(x.size, 1023)
-    assert int((tot * x).sum()) >= 1 << 32
-    pk = np.concatenate([synth.encode_tdc(trig[:1], [0]),
-                         synth.encode_pixels(x, y, tot, t),
-                         synth.encode_tdc(trig[1:], [1])])
+    pk = big_component_packets()
     ref, _ = orc.run(pk)
-    assert ref.size == 1 and ref["npix"][0] == x.size
-    h, _ = tpx.process_stream(pk)
-    assert_hits_match(h, ref)
+    assert ref.size == 1 and ref["npix"][0] == 36992
+    for k in range(-1, tpx.kernel_count()):
+        h, _ = tpx.process_stream(pk, kernel=k)
+        assert_hits_match(h, ref)
 
 
 def test_streams_concurrent_on_two_hip_streams(tpx, orc):
