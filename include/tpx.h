@@ -150,6 +150,21 @@ tpx_status tpx_cluster(tpx_events ev, size_t n_ev, const tpx_params* p_h,
                        uint32_t* labels, size_t* n_clusters_h, void* ws,
                        size_t ws_bytes, void* stream);
 
+/* tpx_cluster for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same arguments and results without a workspace argument.  The
+ * workspace is a 64 MiB array in the library's own device memory (one per
+ * GPU, held until the process ends, its address looked up on the first call
+ * on each device); this call makes no hipMalloc, hipFree or other allocating
+ * call.  n_ev may be at most tpx_cluster_static_max_events() (493,275
+ * events); larger inputs return TPX_EINVAL before any launch.  Every
+ * call on one GPU shares that array: calls that overlap on one GPU (two host
+ * threads, or two HIP streams without ordering between them) race and must
+ * be serialised by the caller.  Synchronises `stream` like tpx_cluster. */
+size_t tpx_cluster_static_max_events(void);
+tpx_status tpx_cluster_static(tpx_events ev, size_t n_ev, const tpx_params* p_h,
+                              uint32_t* labels, size_t* n_clusters_h, void* stream);
+
 /* The paper's own hits (Sec. V, Local Maxima and Centroiding; Eqs. 6-7 and
  * Eq. 9 on A itself), event mode.  Event i is a hit when no neighbour (same
  * shot, |dx| <= dxy, |dy| <= dxy, |ToA difference| <= dt_ticks) carries more

@@ -75,7 +75,7 @@ EXPORTS = ("tpx_params_default", "tpx_unwrap_state_init", "tpx_workspace_bytes",
            "tpx_stream_set_segment", "tpx_stream_get_segment", "tpx_stream_autotune",
            "tpx_stream_patch_workspace_bytes", "tpx_stream_patches", "tpx_stream_set_patches",
            "tpx_stream_kernel_count", "tpx_stream_kernel_name", "tpx_stream_set_kernel",
-           "tpx_stream_get_kernel")
+           "tpx_stream_get_kernel", "tpx_cluster_static", "tpx_cluster_static_max_events")
 
 _lib = None
 
@@ -97,6 +97,10 @@ def load(path=LIB_PATH):
     lib.tpx_workspace_bytes.restype = S
     lib.tpx_decode.argtypes = [P, S, P, P, Events, S, P, S, P, P, P, P, S, P]
     lib.tpx_cluster.argtypes = [Events, S, P, P, P, P, S, P]
+    lib.tpx_cluster_static.argtypes = [Events, S, P, P, P, P]
+    lib.tpx_cluster_static.restype = I
+    lib.tpx_cluster_static_max_events.argtypes = []
+    lib.tpx_cluster_static_max_events.restype = S
     lib.tpx_centroid.argtypes = [Events, P, S, P, S, P, P, S, P, P, S, P]
     lib.tpx_local_maxima.argtypes = [Events, S, P, S, P, P, S, P, P, S, P]
     lib.tpx_stream_create.argtypes = [P, S, P]

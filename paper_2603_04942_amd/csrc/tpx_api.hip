@@ -4,6 +4,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -201,6 +202,43 @@ void launch_front(const uint64_t* pk, uint64_t n, const tpx_params& p, const Dec
 }  // namespace
 
 // ====================================================================== ABI
+// ------------------------------------------------- allocation-free clustering
+// tpx_cluster_static's workspace: a file-scope device array (each GPU the
+// library runs on holds its own copy until the process ends).  In host code
+// the array's name is not a device address: the address is taken once per
+// device with hipGetSymbolAddress and only that address is used.
+constexpr size_t kScratchBytes = 64ull << 20;
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];  // per device: the address of `scratch`, or null
+
+// The current device's copy of `scratch` (looked up on the first call on
+// that device); null with the error reported.
+void* scratch_of_current_device() {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        (void)hipGetLastError();
+        report(TPX_EHIP, "no current HIP device (or more devices than the library tracks)");
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            report(TPX_EHIP, "hipGetSymbolAddress of the static workspace failed");
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+}  // namespace
+
 extern "C" {
 
 void tpx_params_default(tpx_params* p) {
@@ -377,6 +415,31 @@ tpx_status tpx_cluster(tpx_events ev, size_t n_ev, const tpx_params* p_h, uint32
     if ((rc = res_error(r))) return rc;
     if (n_clusters_h) *n_clusters_h = r.n_hits;
     return TPX_OK;
+}
+
+size_t tpx_cluster_static_max_events(void) {
+    // largest n whose workspace fits the static array (the workspace grows
+    // monotonically with n): bisection over the sizing pass
+    size_t lo = 0, hi = kScratchBytes;
+    while (lo < hi) {
+        const size_t mid = lo + (hi - lo + 1) / 2;
+        if (tpx_workspace_bytes(0, mid) <= kScratchBytes) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+tpx_status tpx_cluster_static(tpx_events ev, size_t n_ev, const tpx_params* p_h, uint32_t* labels,
+                              size_t* n_clusters_h, void* stream) {
+    const size_t need = tpx_workspace_bytes(0, n_ev);
+    if (need > kScratchBytes)
+        return fail(TPX_EINVAL, "%zu events need %zu bytes of workspace; the static workspace "
+                    "holds %zu (at most %zu events)", n_ev, need, kScratchBytes,
+                    tpx_cluster_static_max_events());
+    void* ws = scratch_of_current_device();
+    if (!ws) return TPX_EHIP;
+    // every buffer of the workspace that must start at zero is cleared by a
+    // kernel inside tpx_cluster (no memset nodes, no allocation)
+    return tpx_cluster(ev, n_ev, p_h, labels, n_clusters_h, ws, kScratchBytes, stream);
 }
 
 tpx_status tpx_local_maxima(tpx_events ev, size_t n_ev, const uint64_t* trig_toa, size_t n_trig,

@@ -36,6 +36,7 @@
 // ------------------------------------------------------------ qualifiers
 #define __global__
 #define __device__
+#define __align__(n) alignas(n)
 #define __host__
 #define __forceinline__ inline
 #define __launch_bounds__(...)
@@ -327,6 +328,13 @@ hipError_t hipPeekAtLastError();
 hipError_t hipDeviceSynchronize();
 hipError_t hipGetDevice(int* d);
 hipError_t hipSetDevice(int d);
+// a file-scope device array is an ordinary host array here: its symbol is
+// its address
+#define HIP_SYMBOL(x) ((const void*)&(x))
+inline hipError_t hipGetSymbolAddress(void** p, const void* sym) {
+    *p = const_cast<void*>(sym);
+    return hipSuccess;
+}
 const char* hipGetErrorString(hipError_t e);
 
 #define hipLaunchKernelGGL(K, G, B, SH, ST, ...) \
