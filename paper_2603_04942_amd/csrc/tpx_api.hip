@@ -581,6 +581,10 @@ struct tpx_stream {
     uint32_t* big[6];
     uint64_t* g_acc;
     tpx_hit* hits_tmp;      // staged hits of the fused kernel
+    // staged assignment: kept events (and shots) per tile, per-tile records
+    uint64_t* ev_stage;
+    uint32_t *shot_stage, *tile_cnt, *tile_lo, *tile_hi, *tile_off;
+    unsigned long long* tile_stat;
     uint32_t* hit_index;    // hit of every event of the last call (when kept)
     // committed host state
     int64_t pix_epoch, tdc_epoch;
@@ -636,6 +640,24 @@ void free_stream(tpx_stream* s) {
 
 void mark(tpx_stream* s, int i, hipStream_t hs) {
     if (s->timing) (void)hipEventRecord(s->tev[i], hs);
+}
+
+// shot assignment of the chunk's pixels: tiles into their staging ranges,
+// a prefix sum of the tiles' counts, then every kept event to
+// ev[n_carry + its position] (and its shot to shot_final when given)
+void stream_assign(tpx_stream* s, AssignArgs a, uint32_t* shot_final, hipStream_t hs) {
+    const uint64_t nt = ntiles_of(a.n);
+    a.ev = s->ev_stage;
+    a.ev_off = 0;
+    a.ev_cap = nt * kTilePkts;
+    a.shot_out = shot_final ? s->shot_stage : nullptr;
+    a.tile_cnt = s->tile_cnt;
+    a.tile_lo = s->tile_lo;
+    a.tile_hi = s->tile_hi;
+    a.tile_stat = s->tile_stat;
+    launch_assign_staged(a, hs);
+    launch_scan_u32(s->tile_cnt, s->tile_off, nt, nullptr, s->block_tmp, hs);
+    launch_assign_place(a, s->tile_off, s->ev, s->n_carry, s->ev_cap, shot_final, hs);
 }
 
 ClusterArgs stream_cluster_args(tpx_stream* s, tpx_hit* hits, uint64_t hit_cap) {
@@ -748,7 +770,7 @@ tpx_status stream_fast(tpx_stream* s, const uint64_t* chunk, uint64_t n, int flu
     AssignArgs a = stream_assign_args(s, chunk, n);
     a.shot_cnt = s->shot_cnt;
     mark(s, 2, hs);
-    launch_assign(a, false, hs);
+    stream_assign(s, a, nullptr, hs);
     mark(s, 3, hs);
     launch_set_rows(s->res, s->n_win, hs);
     launch_scan_u32(s->shot_cnt, s->shot_off, 0, &s->res->n_groups, s->block_tmp, hs);
@@ -784,8 +806,7 @@ tpx_status stream_general(tpx_stream* s, const uint64_t* chunk, uint64_t n, int 
     launch_carry_in(s->c_ev[s->cur], s->c_shot[s->cur], s->n_carry, s->carry_rebase, s->ev,
                     s->shot_arr, nullptr, hs);
     AssignArgs a = stream_assign_args(s, chunk, n);
-    a.shot_out = s->shot_arr;
-    launch_assign(a, false, hs);
+    stream_assign(s, a, s->shot_arr, hs);
     const uint64_t N = s->n_carry + n_kept;
     const uint64_t n_tab = s->n_win + n_trig;
     HIPCHK(hipMemcpyAsync(s->keys, s->shot_arr, N * 4, hipMemcpyDeviceToDevice, hs));
@@ -860,6 +881,13 @@ tpx_status tpx_stream_create(const tpx_params* p_h, size_t max_chunk_pkts, tpx_s
     ALLOC(s->shot_cnt, s->tab_cap + 2);
     ALLOC(s->shot_off, s->tab_cap + 2);
     ALLOC(s->ev, s->ev_cap);
+    ALLOC(s->ev_stage, nt * kTilePkts);
+    ALLOC(s->shot_stage, nt * kTilePkts);
+    ALLOC(s->tile_cnt, nt);
+    ALLOC(s->tile_lo, nt);
+    ALLOC(s->tile_hi, nt);
+    ALLOC(s->tile_off, nt + 2);
+    ALLOC(s->tile_stat, 8 * nt);
     for (int k = 0; k < 2; ++k) {
         ALLOC(s->c_ev[k], s->carry_cap);
         ALLOC(s->c_shot[k], s->carry_cap);

@@ -268,7 +268,10 @@ __device__ inline uint64_t upper_bound_u64(P a, uint64_t lo, uint64_t hi, uint64
 }
 
 // ------------------------------------------------------------------- assign
-template <bool kSoA>
+// kStaged (packed output only): tile = workgroup index, no look-back; the
+// kept events go to the tile's own staging range and the tile's counts,
+// shot range and statistics to per-tile records.
+template <bool kSoA, bool kStaged = false>
 __global__ __launch_bounds__(kTileThreads) void k_assign(AssignArgs a) {
     __shared__ uint64_t sp[kTileLds];
     __shared__ uint64_t slice[kTrigSlice + 1];
@@ -278,9 +281,14 @@ __global__ __launch_bounds__(kTileThreads) void k_assign(AssignArgs a) {
     __shared__ uint64_t bcast[2];
     constexpr uint32_t kNo = 0xFFFFFFFFu;
 
-    if (threadIdx.x == 0) bcast[0] = atomicAdd(&a.res->tile_ticket, 1ull);
-    __syncthreads();
-    const uint32_t tile = __builtin_amdgcn_readfirstlane((uint32_t)bcast[0]);
+    uint32_t tile;
+    if constexpr (kStaged) {
+        tile = blockIdx.x;
+    } else {
+        if (threadIdx.x == 0) bcast[0] = atomicAdd(&a.res->tile_ticket, 1ull);
+        __syncthreads();
+        tile = __builtin_amdgcn_readfirstlane((uint32_t)bcast[0]);
+    }
     const uint64_t base = (uint64_t)tile * kTilePkts;
     load_tile(a.pk, base, a.n, sp);
     const TileEntry e = a.entries[tile];
@@ -452,8 +460,27 @@ __global__ __launch_bounds__(kTileThreads) void k_assign(AssignArgs a) {
     const bool bad = !sorted || (nkeep && first_s + 1 < mex);
     const bool tile_bad = __syncthreads_or(bad) != 0;
 
-    // look-back over tiles: kept events and largest kept shot before this tile
-    if (w == 0) {
+    if constexpr (kStaged) {
+        // per-tile records instead of a look-back
+        if (threadIdx.x == 0) {
+            a.tile_cnt[tile] = tile_keep;
+            a.tile_lo[tile] = tile_keep ? tile_min : kNo;
+            a.tile_hi[tile] = tile_max1;
+            if (tile_bad) atomicOr(&a.res->unsorted, 1ull);
+            unsigned long long* st = a.tile_stat + 8ull * tile;
+#pragma unroll
+            for (int k = 0; k < 7; ++k) {
+                unsigned long long v = 0;
+                for (int q = 0; q < kWaves; ++q) v += w_stat[q][k];
+                st[k] = v;
+            }
+            unsigned long long mx = 0;
+            for (int q = 0; q < kWaves; ++q) mx = max(mx, w_stat[q][7]);
+            st[7] = mx;
+            bcast[1] = 0;
+        }
+    } else if (w == 0) {
+        // look-back over tiles: kept events and largest kept shot before this tile
         const uint64_t mine = (uint64_t)tile_keep | ((uint64_t)tile_max1 << 31);
         uint64_t prefix;
         if (tile == 0) {
@@ -486,7 +513,7 @@ __global__ __launch_bounds__(kTileThreads) void k_assign(AssignArgs a) {
     if (err) atomicOr(&a.res->err, err);
     __syncthreads();
     const uint64_t pcount = bcast[1] & LbCountMax::kLow;
-    const uint64_t out0 = a.ev_off + pcount;
+    const uint64_t out0 = kStaged ? (uint64_t)tile * kTilePkts : a.ev_off + pcount;
 
     if constexpr (kSoA) {
         uint64_t o = out0 + tpre;
@@ -580,6 +607,96 @@ void launch_trig_unwrap(const TileAcc* sums, const TileAcc* partial, const TileA
     hipLaunchKernelGGL(k_trig_unwrap, dim3((unsigned)((ntiles + 255) / 256)), dim3(256), 0, s,
                        sums, partial, blk, slot, ntiles, tile_scan_blocks(ntiles), pe0, te0, jump,
                        entries, tab, res);
+}
+
+void launch_assign_staged(const AssignArgs& a, hipStream_t s) {
+    const uint64_t ntiles = (a.n + kTilePkts - 1) / kTilePkts;
+    if (ntiles == 0) return;
+    hipLaunchKernelGGL((k_assign<false, true>), dim3((unsigned)ntiles), dim3(kTileThreads), 0, s,
+                       a);
+}
+
+// Staged kept events of tile t to their place; the shot order across tiles
+// (a tile's smallest kept shot below the largest of the nearest earlier tile
+// with kept events, or of the carried events); the call's kept-event count.
+constexpr int kPlaceThreads = 256;
+__global__ __launch_bounds__(kPlaceThreads) void k_assign_place(AssignArgs a, const uint32_t* tile_off,
+                                                                uint64_t* ev_out, uint64_t ev_off,
+                                                                uint64_t ev_cap,
+                                                                uint32_t* shot_final,
+                                                                uint64_t ntiles) {
+    const uint64_t t = blockIdx.x;
+    if (t == 0 && threadIdx.x == 0) a.res->n_kept = tile_off[ntiles];
+    const uint32_t cnt = a.tile_cnt[t];
+    const uint64_t src = t * kTilePkts, dst = ev_off + tile_off[t];
+    for (uint32_t k = threadIdx.x; k < cnt; k += kPlaceThreads) {
+        if (dst + k >= ev_cap) break;
+        ev_out[dst + k] = a.ev[src + k];
+        if (shot_final) shot_final[dst + k] = a.shot_out[src + k];
+    }
+    if (threadIdx.x == 0 && cnt) {
+        // the nearest earlier tile with kept events holds kept position
+        // tile_off[t] - 1: the last t' < t with tile_off[t'] <= it
+        uint64_t prev_max1 = a.carry_last1;
+        const uint32_t before = tile_off[t];
+        if (before > 0) {
+            uint64_t lo = 0, hi = t;  // tile_off[lo] <= before - 1 < tile_off[hi]
+            while (hi - lo > 1) {
+                const uint64_t mid = (lo + hi) >> 1;
+                if (tile_off[mid] <= before - 1) lo = mid; else hi = mid;
+            }
+            prev_max1 = a.tile_hi[lo];
+        }
+        if (prev_max1 > (uint64_t)a.tile_lo[t] + 1) atomicOr(&a.res->unsorted, 1ull);
+    }
+}
+
+// Sum of the per-tile statistics (and the largest unwrapped time + 1).
+constexpr int kStatBlocks = 64;
+__global__ __launch_bounds__(256) void k_tile_stat_reduce(const unsigned long long* st, uint64_t ntiles,
+                                                          DevResults* res) {
+    __shared__ unsigned long long part[256 / 64][8];
+    unsigned long long v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < ntiles;
+         t += (uint64_t)gridDim.x * blockDim.x) {
+#pragma unroll
+        for (int k = 0; k < 7; ++k) v[k] += st[8 * t + k];
+        v[7] = max(v[7], st[8 * t + 7]);
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        for (int d = 32; d > 0; d >>= 1) {
+            const unsigned long long o = __shfl_xor(v[k], d, 64);
+            v[k] = k < 7 ? v[k] + o : max(v[k], o);
+        }
+    const int w = threadIdx.x >> 6;
+    if (__lane_id() == 0)
+        for (int k = 0; k < 8; ++k) part[w][k] = v[k];
+    __syncthreads();
+    if (threadIdx.x < 8) {
+        const int k = threadIdx.x;
+        unsigned long long x = 0;
+        for (int q = 0; q < 256 / 64; ++q) x = k < 7 ? x + part[q][k] : max(x, part[q][k]);
+        unsigned long long* dst[7] = {&res->n_pixels, &res->n_other, &res->n_pre_trigger,
+                                      &res->n_tof_cut, &res->n_late_drop, &res->n_pix_wraps,
+                                      &res->n_pix_backjumps};
+        if (k < 7) {
+            if (x) atomicAdd(dst[k], x);
+        } else if (x) {
+            atomicMax(&res->max_t_plus1, x);
+        }
+    }
+}
+
+void launch_assign_place(const AssignArgs& a, const uint32_t* tile_off, uint64_t* ev_out,
+                         uint64_t ev_off, uint64_t ev_cap, uint32_t* shot_out_final,
+                         hipStream_t s) {
+    const uint64_t ntiles = (a.n + kTilePkts - 1) / kTilePkts;
+    if (ntiles == 0) return;
+    hipLaunchKernelGGL(k_assign_place, dim3((unsigned)ntiles), dim3(kPlaceThreads), 0, s, a,
+                       tile_off, ev_out, ev_off, ev_cap, shot_out_final, ntiles);
+    hipLaunchKernelGGL(k_tile_stat_reduce, dim3(kStatBlocks), dim3(256), 0, s, a.tile_stat, ntiles,
+                       a.res);
 }
 
 void launch_assign(const AssignArgs& a, bool soa, hipStream_t s) {

@@ -30,6 +30,11 @@ struct AssignArgs {
     uint64_t carry_last1;      // table index + 1 of the last event in front (0 = none)
     uint64_t* lb_status;       // zeroed, one word per tile
     DevResults* res;
+    // staged packed output (launch_assign_staged): tile t writes its kept
+    // events at ev[t * kTilePkts ..] and its count, smallest and largest
+    // kept shot (+1) and statistics here
+    uint32_t *tile_cnt, *tile_lo, *tile_hi;
+    unsigned long long* tile_stat;  // 8 per tile
 };
 
 struct ClusterArgs {
@@ -75,6 +80,16 @@ void launch_trig_unwrap(const TileAcc* sums, const TileAcc* partial, const TileA
                         hipStream_t s);
 uint64_t tile_scan_blocks(uint64_t ntiles);
 void launch_assign(const AssignArgs& a, bool soa, hipStream_t s);
+// Stream path without a look-back over tiles: every tile writes its kept
+// events (and shots, when a.shot_out) to its own range of a.ev / a.shot_out
+// (staging) with per-tile counts; then launch_assign_place moves them to
+// ev_out[ev_off + prefix] (shot_out_final likewise), checks the shot order
+// across tiles and reduces the statistics.  tile_off: ntiles + 1 words
+// (exclusive prefix of tile_cnt, filled by the caller's scan).
+void launch_assign_staged(const AssignArgs& a, hipStream_t s);
+void launch_assign_place(const AssignArgs& a, const uint32_t* tile_off, uint64_t* ev_out,
+                         uint64_t ev_off, uint64_t ev_cap, uint32_t* shot_out_final,
+                         hipStream_t s);
 void launch_cluster(const ClusterArgs& a, bool event_mode, uint64_t grid, hipStream_t s);
 // segment table of a group offset array (see ClusterArgs::seg_lo); needs
 // max_events / q + 2 entries
