@@ -1234,8 +1234,10 @@ __device__ uint32_t fused_big(const ClusterArgs& a, uint8_t* lds, uint32_t* scan
     return running;
 }
 
-template <int kYB, int kNT, int kSeg>
-__global__ __launch_bounds__(kNT) void k_cluster_fused(ClusterArgs a) {
+// kWaves: waves per SIMD the register allocation must allow (0: no bound)
+template <int kYB, int kNT, int kSeg, int kWaves = 0>
+__global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(kWaves ? kWaves : 1)))
+void k_cluster_fused(ClusterArgs a) {
     using C = FusedCfg<kYB, kNT, kSeg>;
     constexpr int kE = C::kE;
     __shared__ __attribute__((aligned(16))) uint8_t lds[C::kBytes];
@@ -1323,14 +1325,18 @@ __global__ __launch_bounds__(kNT) void k_cluster_fused(ClusterArgs a) {
             }
         }
         __syncthreads();
-        // 2. neighbours in the 3x3 box: the nine list heads are read
-        // together, then their keys and links together (two LDS round trips
-        // when no list holds more than one event; longer lists are walked
-        // afterwards).  The parent of each event becomes its smallest
-        // neighbour (or itself), a forest whose trees are mostly whole
-        // already; the smaller neighbours (up to 8) stay in registers.
+        // 2. neighbours in the backward half of the 3x3 box (the three slots
+        // of the row above, the slot to the left and the event's own slot),
+        // so that every edge is seen by exactly one of its ends (own slot:
+        // by the later event).  The five list heads are read together, then
+        // their keys and links, then those of the second events (two or
+        // three LDS round trips when no list holds more than two events;
+        // longer lists are walked afterwards).  Every event's parent becomes
+        // the smallest of itself and its neighbours (atomic minimum from both
+        // ends of each edge): a forest whose trees are mostly whole already.
+        // The edges (up to 8 per event) stay in registers.
         uint32_t nb[kE][4];
-        uint32_t meta[kE];  // count of smaller neighbours (bits 0-7), live edges (8-15)
+        uint32_t meta[kE];  // edges kept (bits 0-7), live edges (8-15)
         bool ok = true;
 #pragma unroll
         for (int q = 0; q < kE; ++q) {
@@ -1342,34 +1348,37 @@ __global__ __launch_bounds__(kNT) void k_cluster_fused(ClusterArgs a) {
             const int x = (int)(xy & 255u), y = (int)((xy >> 8) & 255u);
             const uint32_t ki = key[i];
             const uint32_t ti = ki & 0xFFFFu, gs = ki >> C::kGShift;
-            uint32_t head[9], want[3];
+            const uint32_t want_up = C::hi(gs, (uint32_t)(y - 1)), want_row = C::hi(gs, (uint32_t)y);
+            constexpr int kDx[5] = {-1, 0, 1, -1, 0};
+            constexpr int kDy[5] = {-1, -1, -1, 0, 0};
+            uint32_t head[5];
 #pragma unroll
-            for (int r = 0; r < 3; ++r) want[r] = C::hi(gs, (uint32_t)(y + r - 1));
-#pragma unroll
-            for (int s = 0; s < 9; ++s) {
-                const int nx = x + s % 3 - 1, ny = y + s / 3 - 1;
-                const bool in = nx >= 0 && nx <= 255 && ny >= 0 && ny <= 255;
+            for (int s = 0; s < 5; ++s) {
+                const int nx = x + kDx[s], ny = y + kDy[s];
+                const bool in = nx >= 0 && nx <= 255 && ny >= 0;
                 head[s] = in ? head16[C::slot((uint32_t)nx, (uint32_t)ny)] : kNone16;
             }
-            uint32_t hk[9], hn[9];
+            uint32_t hk[5], hn[5];
 #pragma unroll
-            for (int s = 0; s < 9; ++s) {
+            for (int s = 0; s < 5; ++s) {
                 const uint32_t j = head[s] == kNone16 ? i : head[s];
                 hk[s] = key[j];
                 hn[s] = head[s] == kNone16 ? kNone16 : nxt[j];
             }
-            // second element of every list, read together
-            uint32_t k2[9], n2[9];
+            uint32_t k2[5], n2[5];
 #pragma unroll
-            for (int s = 0; s < 9; ++s) {
+            for (int s = 0; s < 5; ++s) {
                 const uint32_t j = hn[s] == kNone16 ? i : hn[s];
                 k2[s] = key[j];
                 n2[s] = hn[s] == kNone16 ? kNone16 : nxt[j];
             }
             uint32_t m = i, c = 0;
-            auto take = [&](uint32_t j, uint32_t kj, uint32_t w) {
-                if (j < i && (kj >> 16) == w && absdiff(kj & 0xFFFFu, ti) <= dt) {
-                    m = j < m ? j : m;
+            auto take = [&](uint32_t j, uint32_t kj, int s) {
+                const uint32_t w = s < 3 ? want_up : want_row;
+                if ((s < 4 || j < i) && j != i && (kj >> 16) == w &&
+                    absdiff(kj & 0xFFFFu, ti) <= dt) {
+                    if (j < m) m = j;
+                    if (j > i) atomicMin(par + j, i);
                     const uint32_t wd = (c >> 1) & 3u, sh16 = (c & 1u) * 16u;
                     if (c < 8) {
                         nb[q][0] |= wd == 0 ? j << sh16 : 0u;
@@ -1381,18 +1390,18 @@ __global__ __launch_bounds__(kNT) void k_cluster_fused(ClusterArgs a) {
                 }
             };
 #pragma unroll
-            for (int s = 0; s < 9; ++s) {
-                if (head[s] != kNone16) take(head[s], hk[s], want[s / 3]);
-                if (hn[s] != kNone16) take(hn[s], k2[s], want[s / 3]);
+            for (int s = 0; s < 5; ++s) {
+                if (head[s] != kNone16) take(head[s], hk[s], s);
+                if (hn[s] != kNone16) take(hn[s], k2[s], s);
             }
             bool longer = false;
 #pragma unroll
-            for (int s = 0; s < 9; ++s) longer |= n2[s] != kNone16;
+            for (int s = 0; s < 5; ++s) longer |= n2[s] != kNone16;
             if (longer) {
-                for (int s = 0; s < 9; ++s) {
+                for (int s = 0; s < 5; ++s) {
                     uint32_t j = n2[s], steps = 0;
                     while (j != kNone16) {
-                        take(j, key[j], want[s / 3]);
+                        take(j, key[j], s);
                         if (++steps > n) {
                             ok = false;
                             break;
@@ -1402,7 +1411,7 @@ __global__ __launch_bounds__(kNT) void k_cluster_fused(ClusterArgs a) {
                 }
             }
             meta[q] = (c < 255 ? c : 255) | ((c > 8 ? 0xFFu : (1u << c) - 1u) << 8);
-            par[i] = m;
+            if (m < i) atomicMin(par + i, m);
         }
         if (!ok) atomicOr(err, (unsigned long long)kErrLoopChain);
         __syncthreads();
@@ -1451,14 +1460,15 @@ __global__ __launch_bounds__(kNT) void k_cluster_fused(ClusterArgs a) {
                     const int x = (int)(xy & 255u), y = (int)((xy >> 8) & 255u);
                     const uint32_t ki = key[i];
                     const uint32_t ti = ki & 0xFFFFu, gs = ki >> C::kGShift;
-                    for (int s = 0; s < 9; ++s) {
-                        const int nx = x + s % 3 - 1, ny = y + s / 3 - 1;
-                        if (nx < 0 || nx > 255 || ny < 0 || ny > 255) continue;
+                    for (int s = 0; s < 5; ++s) {
+                        const int nx = x + (s == 3 ? -1 : s == 4 ? 0 : s - 1), ny = y - (s < 3 ? 1 : 0);
+                        if (nx < 0 || nx > 255 || ny < 0) continue;
                         const uint32_t w = C::hi(gs, (uint32_t)ny);
                         uint32_t j = head16[C::slot((uint32_t)nx, (uint32_t)ny)], steps = 0;
                         while (j != kNone16) {
                             const uint32_t kj = key[j];
-                            if (j < i && (kj >> 16) == w && absdiff(kj & 0xFFFFu, ti) <= dt) {
+                            if ((s < 4 || j < i) && j != i && (kj >> 16) == w &&
+                                absdiff(kj & 0xFFFFu, ti) <= dt) {
                                 const uint32_t r2 = ald(par + j);
                                 if (r2 != ri) {
                                     atomicMin(par + (r2 < ri ? ri : r2), r2 < ri ? r2 : ri);
@@ -1641,9 +1651,9 @@ struct FusedVariant {
 };
 static const FusedVariant kFusedVariants[] = {
     {"image 256x32, 512 threads, 2048 events in LDS"},
-    {"image 256x16, 512 threads, 2048 events in LDS"},
+    {"image 256x16, 512 threads, 2048 events in LDS, 8 waves per SIMD"},
     {"image 256x64, 512 threads, 2048 events in LDS"},
-    {"image 256x32, 256 threads, 2048 events in LDS"},
+    {"image 256x32, 1024 threads, 2048 events in LDS"},
     {"image 256x64, 1024 threads, 8192 events in LDS"},
 };
 
@@ -1656,9 +1666,9 @@ void launch_cluster_fused(const ClusterArgs& a, uint64_t grid, int variant, hipS
     if (grid == 0) return;
     const dim3 g((unsigned)grid);
     switch (variant) {
-    case 1: hipLaunchKernelGGL((k_cluster_fused<4, 512, 2048>), g, dim3(512), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_cluster_fused<4, 512, 2048, 8>), g, dim3(512), 0, s, a); break;
     case 2: hipLaunchKernelGGL((k_cluster_fused<6, 512, 2048>), g, dim3(512), 0, s, a); break;
-    case 3: hipLaunchKernelGGL((k_cluster_fused<5, 256, 2048>), g, dim3(256), 0, s, a); break;
+    case 3: hipLaunchKernelGGL((k_cluster_fused<5, 1024, 2048>), g, dim3(1024), 0, s, a); break;
     case 4: hipLaunchKernelGGL((k_cluster_fused<6, 1024, 8192>), g, dim3(1024), 0, s, a); break;
     default: hipLaunchKernelGGL((k_cluster_fused<5, 512, 2048>), g, dim3(512), 0, s, a); break;
     }
