@@ -490,6 +490,8 @@ def run_uneven(args, w):
                                      kernels=list(range(-1, tpx.kernel_count())))
     sweep = {f"{tpx.kernel_name(k)} @ {q}": round(v, 4) for (k, q), v in sweep.items()}
     fresh = s.get_state()
+    s.set_timing(True)
+    stages = {}
     reps = max(1, args.steps // 2)
     for _ in range(2):
         s.set_state(fresh)
@@ -501,6 +503,8 @@ def run_uneven(args, w):
         rc, nh, st = s.process_raw(pk, True, hits, cap)
         if rc != 0:
             raise tpx.TpxError(rc, "tpx_process_stream", s.lib.tpx_last_error().decode())
+        for k, v in s.stage_times_ms().items():
+            stages[k] = stages.get(k, 0.0) + v / reps
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / reps
     s.close()
@@ -509,7 +513,7 @@ def run_uneven(args, w):
                          "scale up to 1023",
                 packets=int(n), events=int(st.n_events), hits=int(nh),
                 sweep_ms=sweep, stride=best, kernel=best_k, kernel_name=tpx.kernel_name(best_k),
-                ms_per_step=ms,
+                ms_per_step=ms, stages_ms=stages,
                 events_per_s=st.n_events / (ms * 1e-3))
 
 
@@ -582,19 +586,133 @@ def _cpu_model():
     return "unknown"
 
 
+def _cpu_info():
+    """CPU model and counts from /proc/cpuinfo and the scheduler."""
+    info = {"model": "unknown", "nproc": os.cpu_count()}
+    try:
+        info["affinity"] = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        pass
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                k, _, v = line.partition(":")
+                k, v = k.strip(), v.strip()
+                if k == "model name" and info["model"] == "unknown":
+                    info["model"] = v
+                elif k in ("cpu family", "model", "stepping", "cpu MHz"):
+                    info.setdefault(k if k != "model" else "model_number", v)
+    except OSError:
+        pass
+    return info
+
+
+# pixel times near a split lie within about 1 ms of its trigger: a split
+# trigger at least this far from a pixel-counter wrap gives every pixel of
+# the range the trigger's pixel epoch
+_WRAP_MARGIN_TICKS = 2 * 640_000
+
+
+def shot_ranges(wl, procs):
+    """`procs` contiguous ranges of whole shots of the stream: packet
+    [start, stop) and the counter epochs in force at the start (from the
+    trigger that opens the range)."""
+    S = wl.trig_ticks.size
+    cuts = [0]
+    for i in range(1, procs):
+        k = max(cuts[-1] + 1, S * i // procs)
+        while k < S and (int(wl.trig_ticks[k]) % (1 << 34) < _WRAP_MARGIN_TICKS or
+                         (1 << 34) - int(wl.trig_ticks[k]) % (1 << 34) < _WRAP_MARGIN_TICKS):
+            k += 1
+        if k < S:
+            cuts.append(k)
+    out = []
+    for i, k in enumerate(cuts):
+        start = 0 if i == 0 else int(wl.trig_pos[k])
+        stop = int(wl.trig_pos[cuts[i + 1]]) if i + 1 < len(cuts) else wl.n_packets
+        kw = (dict(pix_epoch0=wl.pix_epoch0, tdc_epoch0=wl.tdc_epoch0) if i == 0 else
+              dict(pix_epoch0=int(wl.trig_ticks[k]) >> 34, tdc_epoch0=int(wl.trig_ticks[k]) >> 36))
+        out.append((start, stop, kw))
+    return out
+
+
 def run_cpu_multicore(pool, wl, procs):
     """The oracle in `procs` concurrent processes (the worker pool forked
-    before the GPU was touched), each on the leading 1/16 of the c2 packets:
-    events of all processes over the slowest one's time."""
-    n = wl.n_packets // 16
-    pk = np.ascontiguousarray(wl.packets[:n])
-    kw = dict(pix_epoch0=wl.pix_epoch0, tdc_epoch0=wl.tdc_epoch0)
-    res = pool.map(_oracle_job, [(pk, kw)] * procs, chunksize=1)
+    before the GPU was touched), each on its own contiguous range of whole
+    shots of the c2 stream, together covering all of it: events of all
+    processes over the slowest one's time."""
+    jobs = [(np.ascontiguousarray(wl.packets[a:b]), kw) for a, b, kw in shot_ranges(wl, procs)]
+    res = pool.map(_oracle_job, jobs, chunksize=1)
     ev = sum(r[0] for r in res)
     t_max = max(r[1] for r in res)
-    return dict(value=ev / t_max, unit="events/s", processes=procs, cpu_model=_cpu_model(),
-                sample=f"first {n} packets of the c2 stream in each of {procs} processes, "
-                       f"slowest {t_max:.1f} s")
+    info = _cpu_info()
+    return dict(value=ev / t_max, unit="events/s", processes=len(jobs), cpu_model=info["model"],
+                cpu=info, events=int(ev),
+                sample=f"the whole c2 stream in {len(jobs)} contiguous ranges of whole shots, one "
+                       f"per process, slowest {t_max:.1f} s")
+
+
+def run_c1(args):
+    """The small workload (c1: 1,000 shots, Poisson(10) hits): one flushed
+    tpx_process_stream call over the whole stream, HIP-event timed on the
+    call's stream; microseconds per call and events/s (the whole input fits
+    the 256 MB last-level cache, so no HBM fraction is claimed)."""
+    import torch
+
+    import paper_2603_04942_amd as tpx
+    import synth
+
+    w = synth.make_config("c1", with_truth=False)
+    pk = torch.from_numpy(w.packets.view(np.int64)).cuda()
+    n = pk.numel()
+    s = tpx.Stream(n, pix_epoch0=w.pix_epoch0, tdc_epoch0=w.tdc_epoch0)
+    cap = n // 2 + 1024
+    hits = torch.empty((cap, 48), dtype=torch.uint8, device="cuda")
+    fresh = s.get_state()
+    for _ in range(5):
+        s.set_state(fresh)
+        rc, nh, st = s.process_raw(pk, True, hits, cap)
+    reps = 50
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ms = 0.0
+    for _ in range(reps):
+        s.set_state(fresh)
+        t0.record()
+        rc, nh, st = s.process_raw(pk, True, hits, cap)
+        t1.record()
+        t1.synchronize()
+        if rc != 0:
+            raise tpx.TpxError(rc, "tpx_process_stream", s.lib.tpx_last_error().decode())
+        ms += t0.elapsed_time(t1)
+    s.close()
+    us = ms * 1e3 / reps
+    return dict(workload="c1: 1,000 shots at 1 kHz, Poisson(10) hits/shot, sigma 0.8 px, 1% dark "
+                         "counts", packets=int(n), events=int(st.n_events), hits=int(nh),
+                us_per_call=us, events_per_s=st.n_events / (us * 1e-6))
+
+
+def run_copy(args):
+    """A plain 1 GiB device-to-device copy, HIP-event timed: the HBM rate
+    this GPU reaches on a streaming kernel (read + write bytes over time)."""
+    import torch
+
+    nb = 1 << 30
+    src = torch.ones(nb // 8, dtype=torch.int64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 10
+    torch.cuda.synchronize()
+    t0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / reps
+    del src, dst
+    return dict(bytes_moved=2 * nb, ms=ms, gbs=2 * nb / (ms * 1e-3) / 1e9,
+                frac_of_peak=2 * nb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS)
 
 
 def main():
@@ -718,6 +836,10 @@ def main():
         # (about 10 particles per shot at 1 kHz, batched on a desktop GPU)
         "paper_acquisition_multiple": 25,
     }
+    out["copy_bandwidth"] = run_copy(args)
+    log(f"copy: {out['copy_bandwidth']}")
+    out["c1"] = run_c1(args)
+    log(f"c1: {out['c1']}")
     if not args.no_latency:
         out["stream_latency"] = run_latency(args)
         log(f"latency: {out['stream_latency']}")
@@ -737,7 +859,7 @@ def main():
                                                        / (n_ev / (args.shots * 1e-3)))
         log(f"cpu baseline: {out['cpu_baseline']}")
         if pool is not None:
-            mc = run_cpu_multicore(pool, wl, args.workers)
+            mc = run_cpu_multicore(pool, wl, min(os.cpu_count() or 1, args.workers))
             mc["acquisition_multiple"] = mc["value"] / (n_ev / (args.shots * 1e-3))
             out["cpu_baseline"]["multicore"] = mc
             log(f"cpu multicore: {mc}")

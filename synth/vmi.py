@@ -173,6 +173,7 @@ class Workload:
     pix_epoch0: int
     tdc_epoch0: int
     trig_ticks: np.ndarray                # int64, absolute, trigger k
+    trig_pos: np.ndarray | None = None    # int64, stream index of trigger k's word
     # per-packet truth (stream order); None when generated without truth
     kind: np.ndarray | None = None        # KIND_*
     t_abs: np.ndarray | None = None       # int64 absolute ticks (pixels, TDCs)
@@ -404,6 +405,8 @@ def _assemble(spec, trig, bounds, results, junk_seq, with_truth):
     hit_chunks = {f: [] for f in ("hit_shot", "hit_x", "hit_y", "hit_t_ns", "hit_sigma")}
     carry = None
     hit_base = 0
+    n_out = 0
+    trig_pos = []
     for (lo, hi), (b, hits) in zip(bounds, results):
         b["hit"] = np.where(b["hit"] >= 0, b["hit"] + hit_base, -1)
         hit_base += hits["hit_shot"].size
@@ -427,6 +430,8 @@ def _assemble(spec, trig, bounds, results, junk_seq, with_truth):
         pk[m] = encode_pixels(b["x"][m], b["y"][m], b["tot"][m], b["t_abs"][m])
         m = b["sub"] == TRIG_SUBTYPE
         pk[m] = encode_tdc(b["t_abs"][m], b["shot"][m], TRIG_SUBTYPE)
+        trig_pos.append(n_out + np.nonzero(m)[0])
+        n_out += pk.size
         m = b["sub"] == FALL_SUBTYPE
         pk[m] = encode_tdc(b["t_abs"][m], b["shot"][m], FALL_SUBTYPE)
         m = (b["kind"] == KIND_OTHER) & (b["sub"] < 0)
@@ -449,7 +454,8 @@ def _assemble(spec, trig, bounds, results, junk_seq, with_truth):
     pix_epoch0 = int(t0[first_pix[0]] // PIX_WRAP_TICKS) if first_pix.size else 0
     tdc_epoch0 = int(t0[first_trg[0]] // TDC_WRAP_TICKS) if first_trg.size else 0
     wl = Workload(spec=spec, packets=packets, pix_epoch0=pix_epoch0,
-                  tdc_epoch0=tdc_epoch0, trig_ticks=trig[:S].copy())
+                  tdc_epoch0=tdc_epoch0, trig_ticks=trig[:S].copy(),
+                  trig_pos=np.concatenate(trig_pos).astype(np.int64) if trig_pos else None)
     if with_truth:
         for f in ("kind", "x", "y", "tot", "t_abs", "shot", "tof", "hit"):
             setattr(wl, f, np.concatenate(chunks[f]))
