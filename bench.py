@@ -517,9 +517,10 @@ def run_uneven(args, w):
                 events_per_s=st.n_events / (ms * 1e-3))
 
 
-def run_paper_mode(args, wl):
-    """The paper's local-maximum hits (tpx_local_maxima) on the decoded c2
-    events: events resident in HBM, HIP-event timing on the call's stream."""
+def run_paper_mode(args, wl, name="c2"):
+    """The paper's local-maximum hits (tpx_local_maxima) on the decoded
+    events of a workload: events resident in HBM, HIP-event timing on the
+    call's stream."""
     import torch
 
     import paper_2603_04942_amd as tpx
@@ -546,8 +547,8 @@ def run_paper_mode(args, wl):
     torch.cuda.synchronize()
     ms = t0.elapsed_time(t1) / reps
     alg = 18 * n + HIT_BYTES * nh
-    return dict(workload="c2 decoded events (SoA in HBM): local maxima of ToT over the 8-neighbourhood "
-                         "within 200 ns, Eq. 9 over each maximum's row",
+    return dict(workload=f"{name} decoded events (SoA in HBM): local maxima of ToT over the "
+                         "8-neighbourhood within 200 ns, Eq. 9 over each maximum's row",
                 events=int(n), hits=int(nh), ms_per_call=ms, value=n / (ms * 1e-3), unit="events/s",
                 algorithmic_bytes=int(alg), achieved_gbs=alg / (ms * 1e-3) / 1e9,
                 frac=alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS)
@@ -845,11 +846,14 @@ def main():
         log(f"latency: {out['stream_latency']}")
     if not args.no_uneven:
         out["uneven"] = run_uneven(args, wl3)
-        del wl3
         log(f"uneven: {out['uneven']}")
     if not args.no_paper_mode:
         out["paper_mode"] = run_paper_mode(args, wl)
         log(f"paper mode: {out['paper_mode']}")
+        if wl3 is not None:
+            out["paper_mode_uneven"] = run_paper_mode(args, wl3, "c3")
+            log(f"paper mode c3: {out['paper_mode_uneven']}")
+    del wl3
     if pool is not None:
         out["learned"] = run_learned(args, pool, out["hits_per_s"])
         log(f"learned: {out['learned']}")

@@ -180,10 +180,10 @@ tpx_status tpx_cluster_static(tpx_events ev, size_t n_ev, const tpx_params* p_h,
  *                 toa_first describe its row
  *   n_hits_h      host: number of hits (also on TPX_ECAPACITY)
  *   ws, ws_bytes  device workspace of at least tpx_workspace_bytes(0, n_ev)
+ * Shots of any size: a group of shots larger than the 2,048 events one
+ * workgroup holds in LDS keeps its per-event arrays in the workspace.
  * Errors: TPX_EINVAL (NULL pointers, x or y > 255, ToT > 1023, a shot value
- * >= n_trig), TPX_ECAPACITY (hit_cap too small, or a group of shots that
- * does not fit one 2,048-event segment: shots of up to 1,536 events always
- * fit).  Synchronises the stream. */
+ * >= n_trig), TPX_ECAPACITY (hit_cap too small).  Synchronises the stream. */
 tpx_status tpx_local_maxima(tpx_events ev, size_t n_ev, const uint64_t* trig_toa, size_t n_trig,
                             const tpx_params* p, tpx_hit* hits, size_t hit_cap, size_t* n_hits_h,
                             void* ws, size_t ws_bytes, void* stream);

@@ -495,6 +495,12 @@ tpx_status tpx_local_maxima(tpx_events ev, size_t n_ev, const uint64_t* trig_toa
     a.hits = hits;
     a.hit_cap = hit_cap;
     a.res = w.res;
+    // per-event scratch of groups too large for LDS
+    a.g_parent = w.big[0];
+    a.g_next = w.big[2];
+    a.g_t = w.big[3];
+    a.g_sl = w.big[4];
+    a.g_xy = w.big[5];
     launch_seg_table(w.grp_off, a.n_grp_dev, a.n_ev_dev, nullptr, kQPaper, n_ev, w.seg_lo, w.res,
                      s);
     const uint64_t grid = cluster_grid(n_ev, kQPaper);
@@ -502,8 +508,6 @@ tpx_status tpx_local_maxima(tpx_events ev, size_t n_ev, const uint64_t* trig_toa
     launch_scan_u32(w.seg_cnt, w.seg_off, 0, &w.res->n_seg, w.block_tmp, s);
     launch_paper(a, trig_toa, true, grid, s);
     if ((rc = read_res(w.res, &r, s))) return rc;
-    if (r.err & kErrCapacity)
-        return fail(TPX_ECAPACITY, "a shot group does not fit one %d-event segment", cluster_capacity());
     if ((rc = res_error(r))) return rc;
     *n_hits_h = r.n_hits;
     if (r.n_hits > hit_cap) return fail(TPX_ECAPACITY, "need %llu hit slots", r.n_hits);

@@ -900,6 +900,143 @@ constexpr int kPOffTot = 61440;        // u16[kCap]
 constexpr int kLdsPaper = 65536;
 static_assert(kPOffTot + 2 * kCap <= kLdsPaper, "paper layout");
 
+// Local maxima of a segment of more than kCap events: per-event arrays in
+// global scratch (pixel address, time, group start, ToT, slot-list link), the
+// image of slot-list heads (u32) in LDS; the same decisions and moments as the
+// LDS path.  Returns the segment's maximum count (count pass) after writing
+// the hits (write pass).
+template <bool kWrite>
+__device__ uint32_t paper_big(const ClusterArgs& a, const uint64_t* __restrict__ trig,
+                              uint8_t* lds, uint32_t* scan_tmp, const uint32_t* goff,
+                              bool goff_lds, const Seg& sg, uint32_t k) {
+    uint32_t* img = (uint32_t*)lds;  // u32[kH], all-ones = empty
+    const uint64_t e0 = sg.e0;
+    const uint32_t n = sg.n;
+    uint32_t* xy = a.g_xy + e0;
+    uint32_t* tt = a.g_t + e0;
+    uint32_t* gs = a.g_sl + e0;
+    uint32_t* tot = a.g_parent + e0;
+    uint32_t* nxt = a.g_next + e0;
+    const int tid = threadIdx.x;
+    const int r = (int)a.dxy;
+    const uint32_t dt = a.dt;
+    unsigned long long* err = &a.res->err;
+    {
+        uint4* v = (uint4*)img;
+        for (int i = tid; i < kH * 4 / 16; i += kWG) v[i] = make_uint4(~0u, ~0u, ~0u, ~0u);
+    }
+    __syncthreads();
+    const uint32_t ng = sg.g_hi - sg.g_lo;
+    for (uint32_t i = tid; i < n; i += kWG) {
+        const uint32_t p = (uint32_t)(e0 + i);
+        const uint32_t g = goff_lds ? sg.g_lo + group_of(goff, 0, ng, p)
+                                    : group_of(a.grp_off, sg.g_lo, sg.g_hi, p);
+        const Ev e = load_event<true>(a, e0 + i, g, e0, err);
+        xy[i] = e.x | (e.y << 8);
+        tt[i] = e.t;
+        gs[i] = e.gs;
+        tot[i] = a.soa.tot[orig_of(a, e0 + i)];
+        nxt[i] = atomicExch(&img[slot_of(e.x, e.y)], i);
+    }
+    __syncthreads();
+    // calls f(j) for every event j != i of the (2r+1)^2 box with an edge to i
+    auto neighbours = [&](uint32_t i, auto&& f) {
+        const uint32_t v = xy[i];
+        const int x = (int)(v & 255u), y = (int)(v >> 8);
+        const uint32_t t = tt[i], g = gs[i];
+        bool ok = true;
+        for (int dy = -r; dy <= r; ++dy) {
+            const int ny = y + dy;
+            if (ny < 0 || ny > 255) continue;
+            for (int dx = -r; dx <= r; ++dx) {
+                const int nx = x + dx;
+                if (nx < 0 || nx > 255) continue;
+                const uint32_t want = (uint32_t)nx | ((uint32_t)ny << 8);
+                uint32_t j = img[slot_of((uint32_t)nx, (uint32_t)ny)], steps = 0;
+                while (j != kNone32) {
+                    if (j != i && xy[j] == want && gs[j] == g && absdiff(tt[j], t) <= dt) f(j);
+                    if (++steps > n) {
+                        ok = false;
+                        break;
+                    }
+                    j = nxt[j];
+                }
+            }
+        }
+        if (!ok) atomicOr(err, (unsigned long long)kErrLoopChain);
+    };
+    uint32_t running = 0;
+    const uint32_t rounds = (n + kWG - 1) / kWG;
+    for (uint32_t rd = 0; rd < rounds; ++rd) {
+        const uint32_t i = rd * kWG + tid;
+        bool is_max = false;
+        if (i < n) {
+            is_max = true;
+            const uint32_t ti = tot[i];
+            neighbours(i, [&](uint32_t j) {
+                const uint32_t tj = tot[j];
+                if (tj > ti || (tj == ti && j > i)) is_max = false;
+            });
+        }
+        uint32_t tot_r;
+        const uint32_t rk = running + wg_flag_scan<kWG>(is_max, scan_tmp, &tot_r);
+        if (kWrite && is_max) {
+            // Eq. (9) over row i of A, exact integer moments
+            const uint64_t oi = orig_of(a, e0 + i);
+            const uint32_t sh = a.soa.shot[oi];
+            const uint64_t T = trig[sh];
+            uint64_t W = 0, cnt = 0, tmin = ~0ull;
+            int64_t Sx = 0, Sy = 0, St = 0, Ux = 0, Uy = 0, Ut = 0;
+            double Sw = 0.0, Uw = 0.0;
+            auto add = [&](uint32_t j) {
+                const uint64_t o = orig_of(a, e0 + j);
+                const uint64_t toa = a.soa.toa[o];
+                const uint32_t vj = xy[j];
+                const int64_t x = (int64_t)(vj & 255u), y = (int64_t)(vj >> 8);
+                const int64_t w = tot[j], tof = (int64_t)(toa - T);
+                W += (uint64_t)w;
+                Sx += w * x;
+                Sy += w * y;
+                St += w * tof;
+                Ux += x;
+                Uy += y;
+                Ut += tof;
+                if (a.walk) {
+                    const double wk = (double)a.walk[w & 1023];
+                    Sw += (double)w * wk;
+                    Uw += wk;
+                }
+                ++cnt;
+                tmin = toa < tmin ? toa : tmin;
+            };
+            add(i);
+            neighbours(i, add);
+            const uint64_t h = a.seg_off[k] + rk;
+            if (h < a.hit_cap) {
+                tpx_hit o;
+                if (W) {
+                    o.x = (float)((double)Sx / (double)W);
+                    o.y = (float)((double)Sy / (double)W);
+                    o.tof_ns = (float)((1.5625 * (double)St - Sw) / (double)W);
+                } else {
+                    o.x = (float)((double)Ux / (double)cnt);
+                    o.y = (float)((double)Uy / (double)cnt);
+                    o.tof_ns = (float)((1.5625 * (double)Ut - Uw) / (double)cnt);
+                }
+                o.npix = (uint32_t)cnt;
+                o.shot = sh;
+                o.label = oi;
+                o.toa_first = tmin;
+                o.tot_sum = (uint32_t)W;
+                o.flags = W ? 0u : 1u;
+                a.hits[h] = o;
+            }
+        }
+        running += tot_r;
+    }
+    return running;
+}
+
 template <bool kWrite>
 __global__ __launch_bounds__(kWG) void k_paper(ClusterArgs a, const uint64_t* __restrict__ trig) {
     __shared__ __attribute__((aligned(16))) uint8_t lds[kLdsPaper];
@@ -918,11 +1055,20 @@ __global__ __launch_bounds__(kWG) void k_paper(ClusterArgs a, const uint64_t* __
     Seg sg;
     if (!seg_bounds(a, k, N, sg)) return;
     const uint32_t n = sg.n;
-    if (n == 0 || n > (uint32_t)kCap) {
-        if (tid == 0) {
-            if (!kWrite) a.seg_cnt[k] = 0;
-            if (n > (uint32_t)kCap) atomicOr(&a.res->err, (unsigned long long)kErrCapacity);
-        }
+    if (n == 0) {
+        if (tid == 0 && !kWrite) a.seg_cnt[k] = 0;
+        return;
+    }
+    if (n > (uint32_t)kCap) {
+        // too large for LDS: the global-memory path
+        const uint32_t ngb = sg.g_hi - sg.g_lo;
+        const bool gl = ngb <= (uint32_t)kWG;
+        if (gl)
+            for (uint32_t i = tid; i <= ngb; i += kWG) goff[i] = a.grp_off[sg.g_lo + i];
+        __syncthreads();
+        const uint32_t cnt = paper_big<kWrite>(a, trig, lds, scan_tmp, goff, gl, sg, k);
+        if (!kWrite && tid == 0) a.seg_cnt[k] = cnt;
+        if (kWrite && k == 0 && tid == 0) a.res->n_hits = a.seg_off[n_seg];
         return;
     }
     const uint64_t e0 = sg.e0;

@@ -103,3 +103,24 @@ def test_errors(tpx):
     ev["shot"][0] = 0
     h = _run(tpx, ev, [0])
     assert h.size == 1 and h["npix"][0] == 1
+
+
+def test_groups_beyond_lds(tpx, orc):
+    """Shot groups larger than the 2,048 events a workgroup holds in LDS take
+    the global-memory path: the uneven-shot workload (its Poisson(200) shots
+    hold several thousand events), one shot of 3,009 events (isolated pixels
+    and a blob) and one of 7,200 equal-ToT pixels (every decision a tie)."""
+    from cases import big_component_packets, many_components_packets
+    w = synth.make_config("c3", n_shots=150)
+    cases = [("c3", w.packets, dict(pix_epoch0=w.pix_epoch0, tdc_epoch0=w.tdc_epoch0)),
+             ("iso3000", many_components_packets(3000), {}),
+             ("square", big_component_packets(side=60, layers=2), {})]
+    for name, pk, kw in cases:
+        d = orc.decode(pk, **kw)
+        e = d["events"]
+        counts = np.bincount(e["shot"].astype(np.int64))
+        _say(f"paper mode {name}: {e['x'].size} events, largest shot {counts.max()}")
+        assert counts.max() > 2048
+        ref = orc.local_maxima(e["x"], e["y"], e["tot"], e["shot"], e["toa"], d["trig"])
+        h = _run(tpx, e, d["trig"])
+        assert_hits_match(h, ref)
