@@ -5,3 +5,4 @@ from .vmi import (GRID, KIND_OTHER, KIND_PIXEL, KIND_TRIGGER, PIX_WRAP_TICKS,  #
                   Spec, Workload, encode_pixels, encode_tdc, generate, make_config,
                   tiny_events)
 from .clusters import init_mlp_params, make_clusters  # noqa: F401,E402
+from .walkcal import WALK_DEFAULT, calibration_run, walk_ns  # noqa: F401,E402
