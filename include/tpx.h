@@ -165,6 +165,32 @@ size_t tpx_cluster_static_max_events(void);
 tpx_status tpx_cluster_static(tpx_events ev, size_t n_ev, const tpx_params* p_h,
                               uint32_t* labels, size_t* n_clusters_h, void* stream);
 
+/* Walk calibration (Sec. IV, ToT-ToF Correlation Correction, Eq. 1) from the
+ * decoded events of a calibration run (one ion species at one true ToF):
+ *   1. the pixels of the ion peak: tof_lo <= ToF <= tof_hi (ticks; ToF =
+ *      toa - trig_toa[shot]);
+ *   2. per ToT value the centre of its ToF distribution: the maximum-
+ *      likelihood centre of a Gaussian, i.e. the slice's mean ToF (ns);
+ *   3. Eq. (1), <ToF>(ToT) = a / (ToT + b)^d + c, fitted to the centres of
+ *      the ToT values with at least min_count pixels by least squares
+ *      weighted by their pixel counts (= a fit over the individual pixels;
+ *      Levenberg-Marquardt on the host, b kept above -min ToT, d in
+ *      [0.05, 8]).
+ * params_h (host, 4): a, b, c, d (ns, ToT counts); c is the peak's ToF.
+ * count_h (host u32[1024], may be NULL): pixels per ToT value in the window;
+ * mean_h (host double[1024], may be NULL): their mean ToF in ns (NaN if none).
+ * lut (device float[1024], may be NULL): walk(ToT) = a / (ToT + b)^d in ns
+ * (ToT values at or below -b take the value of the smallest one above), the
+ * table that tpx_params.walk_lut_ns takes (true ToF = measured - walk).
+ * ws: tpx_walk_fit_workspace_bytes() device bytes.  Errors: TPX_EINVAL (NULL
+ * pointers, tof_hi < tof_lo, min_count 0, a shot without trigger time, fewer
+ * than 4 usable ToT values).  Synchronises the stream. */
+size_t tpx_walk_fit_workspace_bytes(void);
+tpx_status tpx_walk_fit(tpx_events ev, size_t n_ev, const uint64_t* trig_toa, size_t n_trig,
+                        uint64_t tof_lo, uint64_t tof_hi, uint32_t min_count, double* params_h,
+                        uint32_t* count_h, double* mean_h, float* lut, void* ws, size_t ws_bytes,
+                        void* stream);
+
 /* The paper's own hits (Sec. V, Local Maxima and Centroiding; Eqs. 6-7 and
  * Eq. 9 on A itself), event mode.  Event i is a hit when no neighbour (same
  * shot, |dx| <= dxy, |dy| <= dxy, |ToA difference| <= dt_ticks) carries more

@@ -75,7 +75,8 @@ EXPORTS = ("tpx_params_default", "tpx_unwrap_state_init", "tpx_workspace_bytes",
            "tpx_stream_set_segment", "tpx_stream_get_segment", "tpx_stream_autotune",
            "tpx_stream_patch_workspace_bytes", "tpx_stream_patches", "tpx_stream_set_patches",
            "tpx_stream_kernel_count", "tpx_stream_kernel_name", "tpx_stream_set_kernel",
-           "tpx_stream_get_kernel", "tpx_cluster_static", "tpx_cluster_static_max_events")
+           "tpx_stream_get_kernel", "tpx_cluster_static", "tpx_cluster_static_max_events",
+           "tpx_walk_fit", "tpx_walk_fit_workspace_bytes")
 
 _lib = None
 
@@ -99,6 +100,11 @@ def load(path=LIB_PATH):
     lib.tpx_cluster.argtypes = [Events, S, P, P, P, P, S, P]
     lib.tpx_cluster_static.argtypes = [Events, S, P, P, P, P]
     lib.tpx_cluster_static.restype = I
+    lib.tpx_walk_fit_workspace_bytes.argtypes = []
+    lib.tpx_walk_fit_workspace_bytes.restype = S
+    lib.tpx_walk_fit.argtypes = [Events, S, P, S, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32,
+                                 P, P, P, P, P, S, P]
+    lib.tpx_walk_fit.restype = I
     lib.tpx_cluster_static_max_events.argtypes = []
     lib.tpx_cluster_static_max_events.restype = S
     lib.tpx_centroid.argtypes = [Events, P, S, P, S, P, P, S, P, P, S, P]
@@ -537,6 +543,24 @@ def process_stream(packets, flush=True, kernel=None, **kw):
         return s.process(packets, flush=flush)
     finally:
         s.close()
+
+
+def walk_fit(ev, trig, tof_lo, tof_hi, min_count=20):
+    """tpx_walk_fit on device events: dict(params=(a, b, c, d), count, mean,
+    lut=device float tensor [1024])."""
+    torch = _torch()
+    lib = load()
+    t = trig if isinstance(trig, torch.Tensor) else _u64(torch, np.asarray(trig, np.uint64))
+    params = (ctypes.c_double * 4)()
+    count = np.zeros(1024, np.uint32)
+    mean = np.zeros(1024, np.float64)
+    lut = torch.empty(1024, dtype=torch.float32, device="cuda")
+    ws = torch.empty(lib.tpx_walk_fit_workspace_bytes(), dtype=torch.uint8, device="cuda")
+    n = ev["x"].numel()
+    _check(lib.tpx_walk_fit(events_struct(ev), n, _ptr(t), t.numel(), int(tof_lo), int(tof_hi),
+                            int(min_count), params, count.ctypes.data, mean.ctypes.data, _ptr(lut),
+                            _ptr(ws), ws.numel(), _stream(torch)), "tpx_walk_fit")
+    return dict(params=tuple(params), count=count, mean=mean, lut=lut)
 
 
 # ------------------------------------------------------- learned centroider

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libtpx.so")
 SOURCES = ["tpx_decode.hip", "tpx_cluster.hip", "tpx_util.hip", "tpx_api.hip", "tpx_service.hip",
-           "tpx_learn.hip"]
+           "tpx_learn.hip", "tpx_walk.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Wno-unused-function", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
