@@ -307,79 +307,26 @@ def batched_replays(args, tpx, w, pk, chunk, pk_rate):
 
 
 def threaded_replays(args, tpx, w, pk, chunk, pk_rate):
-    """Paced replays through tpx_service: a producer thread admits chunk k when
-    it is released (its copy goes on the service's own stream and overlaps
-    the batch in flight); the main thread runs the service in a loop, each run
-    taking every chunk admitted so far (up to the batch limit).  Latency of a
-    chunk = completion of the run that took it - its release."""
-    import threading
-
-    import torch
-
+    """Paced replays through tpx_service driven by the library's native
+    producer (tpx_service_replay): a producer thread inside the library admits
+    chunk k at its release (its copy goes on the service's own stream and
+    overlaps the batch in flight); the calling thread runs the service in a
+    loop, each run taking every chunk admitted so far (up to the batch limit).
+    Latency of a chunk = completion of the run that took it - its release.
+    No Python runs between a release and its processing."""
     n_pk = pk.numel()
-    starts = list(range(0, n_pk, chunk))
     max_batch = max(1 << 19, 4 * chunk)
-    cap = 2 * max_batch
-    hits = torch.empty((cap, 48), dtype=torch.uint8, device="cuda")
-    res = {"max_batch_packets": max_batch}
+    res = {"max_batch_packets": max_batch, "producer": "native thread in the library"}
     for speed in args.latency_speeds:
-        lim = max(1, min(len(starts), int(2.0 * pk_rate * speed / chunk)))
+        n_chunks = -(-n_pk // chunk)
+        lim = max(1, min(n_chunks, int(2.0 * pk_rate * speed / chunk)))
         sv = tpx.Service(max_batch, pix_epoch0=w.pix_epoch0, tdc_epoch0=w.tdc_epoch0)
-        views = [pk[a:a + chunk] for a in starts[:lim]]
-        # ctypes arguments prepared ahead: at 200x a 64 KiB chunk arrives every
-        # 34 us, about what building them per call costs in Python
-        import ctypes
-        ptrs = [ctypes.c_void_p(v.data_ptr()) for v in views]
-        sizes = [v.numel() for v in views]
-        hstream = tpx._stream(torch)
-        submit = sv.lib.tpx_service_submit
-        t0 = time.perf_counter() + 0.01
-        rel = [t0 + min(a + chunk, n_pk) / pk_rate / speed for a in starts[:lim]]
-        done = threading.Event()
-        errors = []
-
-        def producer():
-            try:
-                for k in range(lim):
-                    # sleep (releasing the interpreter lock) until the release
-                    wait = rel[k] - time.perf_counter()
-                    if wait > 0:
-                        time.sleep(wait)
-                    while True:
-                        rc = submit(sv.h, ptrs[k], sizes[k], 1, None, hstream)
-                        if rc != tpx.ECAPACITY:
-                            break
-                    if rc != 0:
-                        raise tpx.TpxError(rc, "tpx_service_submit",
-                                           sv.lib.tpx_last_error().decode())
-            except Exception as e:  # noqa: BLE001 - re-raised below
-                errors.append(e)
-            finally:
-                done.set()
-
-        th = threading.Thread(target=producer)
-        switch = sys.getswitchinterval()
-        sys.setswitchinterval(1e-4)   # hand the interpreter lock over quickly
-        th.start()
-        lat, done_n, runs = [], 0, 0
-        while done_n < lim and not errors:
-            fin = done.is_set()
-            rc, nh, nd, st = sv.run_raw(fin, hits, cap)
-            t = time.perf_counter()
-            if rc != 0:
-                errors.append(tpx.TpxError(rc, "tpx_service_run", sv.lib.tpx_last_error().decode()))
-                break
-            lat += [(t - rel[k]) * 1e3 for k in range(done_n, nd)]
-            runs += nd > done_n
-            done_n = nd
-        th.join()
-        sys.setswitchinterval(switch)
+        lat, runs = sv.replay(pk[:min(n_pk, lim * chunk)], chunk, pk_rate * speed,
+                              hit_cap=2 * max_batch)
         sv.close()
-        if errors:
-            raise errors[0]
-        res[f"{speed:g}x"] = dict(chunks=lim, runs=runs, p50_ms=float(np.percentile(lat, 50)),
-                                  p99_ms=float(np.percentile(lat, 99)))
-    del hits
+        res[f"{speed:g}x"] = dict(chunks=int(lat.size), runs=runs,
+                                 p50_ms=float(np.percentile(lat, 50)),
+                                 p99_ms=float(np.percentile(lat, 99)))
     return res
 
 
@@ -722,6 +669,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--shots", type=int, default=100_000, help="c2 shots (default: full size)")
+    ap.add_argument("--workload", choices=["c2", "c3"], default="c2",
+                    help="workload of the timed step (c3 only to profile the uneven-shot "
+                         "workload; the headline figure is c2)")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--cpu-frac", type=float, default=1.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -762,7 +712,12 @@ def main():
         import multiprocessing
         pool = multiprocessing.get_context("fork").Pool(args.workers)
     t = time.perf_counter()
-    wl = synth.make_config("c2", n_shots=args.shots, with_truth=False, workers=args.workers)
+    if args.workload == "c3":
+        # profiling the uneven-shot workload: its stream step is the timed step
+        args.no_uneven = True
+        args.shots = 200_000 if args.shots == 100_000 else args.shots
+    wl = synth.make_config(args.workload, n_shots=args.shots, with_truth=False,
+                           workers=args.workers)
     log(f"generated c2: {wl.n_packets} packets in {time.perf_counter() - t:.1f} s")
     wl3 = None
     if not args.no_uneven:
@@ -796,9 +751,13 @@ def main():
         "dtype": "int64",
         "data": "synthetic",
         "config": {
-            "workload": "c2: 100,000 shots at 1 kHz, Poisson(30) hits/shot, sigma U(0.6,1.5) px, "
-                        "10% close pairs, 1% dark counts, TPX3 packets with spidr/ToA rollover "
-                        "and trigger words; 8-connected, |dToA| <= 200 ns",
+            "workload": ("c2: 100,000 shots at 1 kHz, Poisson(30) hits/shot, sigma U(0.6,1.5) px, "
+                         "10% close pairs, 1% dark counts, TPX3 packets with spidr/ToA rollover "
+                         "and trigger words; 8-connected, |dToA| <= 200 ns")
+            if args.workload == "c2" else
+            ("c3: 200,000 shots, hits/shot 0.7 Poisson(5) + 0.25 Poisson(40) + 0.05 "
+             "Poisson(200); 60% sigma 0.5 px, 40% sigma U(1.5, 2.5) px with ToT scale up to "
+             "1023; 8-connected, |dToA| <= 200 ns"),
             "shots": args.shots,
             "packets": int(n_pk),
             "events": int(n_ev),

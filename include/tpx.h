@@ -285,6 +285,8 @@ const char* tpx_stream_stage_name(size_t i);
  * keeps its state, its former q and its former kernel. */
 tpx_status tpx_stream_set_segment(tpx_stream* s, uint32_t q);
 uint32_t tpx_stream_get_segment(const tpx_stream* s);
+/* Device memory the stream holds (sum of its allocations). */
+size_t tpx_stream_device_bytes(const tpx_stream* s);
 int tpx_stream_kernel_count(void);
 const char* tpx_stream_kernel_name(int k);
 tpx_status tpx_stream_set_kernel(tpx_stream* s, int k);
@@ -331,6 +333,58 @@ tpx_status tpx_service_run(tpx_service* sv, int flush, tpx_hit* hits, size_t hit
                            size_t* n_hits_h, uint64_t* n_done_h, tpx_stats* stats_h,
                            void* stream);
 void tpx_service_destroy(tpx_service* sv);
+/*   tpx_service_device_bytes  device memory the service holds (its stream,
+ *                       ring and staging buffer).
+ *   tpx_service_replay  paced replay with a native producer thread: chunk k
+ *                       (chunk words of the device-resident stream pk[n]) is
+ *                       submitted when its last word would have been acquired
+ *                       at pkts_per_s packets per second; the calling thread
+ *                       runs the service whenever chunks are admitted (flush
+ *                       with the last).  lat_ms_h[k] (host, may be NULL) =
+ *                       completion of the run that processed chunk k minus
+ *                       its release; *n_chunks_h chunks, *n_runs_h runs.  The
+ *                       service must hold no unprocessed chunks.  hits /
+ *                       hit_cap receive each run's hits in turn. */
+size_t tpx_service_device_bytes(const tpx_service* sv);
+tpx_status tpx_service_replay(tpx_service* sv, const uint64_t* pk, size_t n, size_t chunk,
+                              double pkts_per_s, tpx_hit* hits, size_t hit_cap, float* lat_ms_h,
+                              size_t lat_cap, size_t* n_chunks_h, uint64_t* n_runs_h,
+                              void* stream);
+
+/* Several independent request streams at once (the streaming workload
+ * served to many clients).  A server holds open slots, each an independent
+ * tpx_service (its own unwrap state, trigger window, ring and staging); a
+ * slot is admitted only while its device memory fits the server's HBM budget,
+ * and slot k's runs go to HIP stream k mod n_streams of the server, so runs of
+ * different slots issued from different host threads overlap on the GPU.
+ * Slots share no state: a slot's hits are the ones it gives alone.
+ *   tpx_server_create  hbm_budget_bytes: device memory the slots may hold
+ *                       together; n_streams: 1..64 HIP streams.
+ *   tpx_server_open    a new slot for a stream with parameters p_h (NULL:
+ *                       the server's) whose chunks hold at most
+ *                       max_batch_pkts words, ring_pkts of admission ring
+ *                       (as tpx_service_create); *slot_h its number (the
+ *                       lowest free), *bytes_h (may be NULL) its device
+ *                       memory.  TPX_ECAPACITY when that exceeds the free
+ *                       budget (nothing stays allocated).
+ *   tpx_server_submit / tpx_server_run  tpx_service_submit / _run on the
+ *                       slot (run on the slot's HIP stream; synchronises it).
+ *   tpx_server_close   frees the slot and returns its memory to the budget.
+ * Calls on one slot follow the service's rules; calls on different slots may
+ * overlap. */
+typedef struct tpx_server tpx_server;
+tpx_status tpx_server_create(const tpx_params* p_h, size_t hbm_budget_bytes, int n_streams,
+                             tpx_server** out_h);
+tpx_status tpx_server_open(tpx_server* sr, const tpx_params* p_h, size_t max_batch_pkts,
+                           size_t ring_pkts, uint32_t* slot_h, size_t* bytes_h);
+tpx_status tpx_server_submit(tpx_server* sr, uint32_t slot, const uint64_t* chunk, size_t n_pkts,
+                             int chunk_on_device, uint64_t* seq_h, void* stream);
+tpx_status tpx_server_run(tpx_server* sr, uint32_t slot, int flush, tpx_hit* hits,
+                          size_t hit_cap, size_t* n_hits_h, uint64_t* n_done_h,
+                          tpx_stats* stats_h);
+tpx_status tpx_server_close(tpx_server* sr, uint32_t slot);
+size_t tpx_server_free_bytes(tpx_server* sr);
+void tpx_server_destroy(tpx_server* sr);
 
 /* Learned centroider / multiplicity splitter.  A small network reads a 7 x 7
  * patch around every hit and predicts up to two hits and their multiplicity;

@@ -76,7 +76,10 @@ EXPORTS = ("tpx_params_default", "tpx_unwrap_state_init", "tpx_workspace_bytes",
            "tpx_stream_patch_workspace_bytes", "tpx_stream_patches", "tpx_stream_set_patches",
            "tpx_stream_kernel_count", "tpx_stream_kernel_name", "tpx_stream_set_kernel",
            "tpx_stream_get_kernel", "tpx_cluster_static", "tpx_cluster_static_max_events",
-           "tpx_walk_fit", "tpx_walk_fit_workspace_bytes")
+           "tpx_walk_fit", "tpx_walk_fit_workspace_bytes", "tpx_stream_device_bytes",
+           "tpx_service_device_bytes", "tpx_service_replay", "tpx_server_create", "tpx_server_open",
+           "tpx_server_submit", "tpx_server_run", "tpx_server_close", "tpx_server_free_bytes",
+           "tpx_server_destroy")
 
 _lib = None
 
@@ -100,6 +103,26 @@ def load(path=LIB_PATH):
     lib.tpx_cluster.argtypes = [Events, S, P, P, P, P, S, P]
     lib.tpx_cluster_static.argtypes = [Events, S, P, P, P, P]
     lib.tpx_cluster_static.restype = I
+    lib.tpx_stream_device_bytes.argtypes = [P]
+    lib.tpx_stream_device_bytes.restype = S
+    lib.tpx_service_device_bytes.argtypes = [P]
+    lib.tpx_service_device_bytes.restype = S
+    lib.tpx_service_replay.argtypes = [P, P, S, S, ctypes.c_double, P, S, P, S, P, P, P]
+    lib.tpx_service_replay.restype = I
+    lib.tpx_server_create.argtypes = [P, S, ctypes.c_int, P]
+    lib.tpx_server_create.restype = I
+    lib.tpx_server_open.argtypes = [P, P, S, S, P, P]
+    lib.tpx_server_open.restype = I
+    lib.tpx_server_submit.argtypes = [P, ctypes.c_uint32, P, S, ctypes.c_int, P, P]
+    lib.tpx_server_submit.restype = I
+    lib.tpx_server_run.argtypes = [P, ctypes.c_uint32, ctypes.c_int, P, S, P, P, P]
+    lib.tpx_server_run.restype = I
+    lib.tpx_server_close.argtypes = [P, ctypes.c_uint32]
+    lib.tpx_server_close.restype = I
+    lib.tpx_server_free_bytes.argtypes = [P]
+    lib.tpx_server_free_bytes.restype = S
+    lib.tpx_server_destroy.argtypes = [P]
+    lib.tpx_server_destroy.restype = None
     lib.tpx_walk_fit_workspace_bytes.argtypes = []
     lib.tpx_walk_fit_workspace_bytes.restype = S
     lib.tpx_walk_fit.argtypes = [Events, S, P, S, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32,
@@ -524,9 +547,90 @@ class Service:
         _check(rc, "tpx_service_run")
         return hits_to_numpy(hits, n), nd, st.as_dict()
 
+    def replay(self, pk, chunk, pkts_per_s, hit_cap=1 << 20):
+        """tpx_service_replay of a device-resident stream: (latencies in ms
+        per chunk, runs)."""
+        torch = self.torch
+        n_chunks = (pk.numel() + chunk - 1) // chunk
+        lat = np.zeros(max(n_chunks, 1), np.float32)
+        hits = torch.empty((max(hit_cap, 1), 48), dtype=torch.uint8, device="cuda")
+        nc, nr = ctypes.c_size_t(), ctypes.c_uint64()
+        _check(self.lib.tpx_service_replay(self.h, _ptr(pk), pk.numel(), chunk, float(pkts_per_s),
+                                           _ptr(hits), hit_cap, lat.ctypes.data, lat.size,
+                                           ctypes.byref(nc), ctypes.byref(nr), _stream(torch)),
+               "tpx_service_replay")
+        return lat[:nc.value], int(nr.value)
+
+    @property
+    def device_bytes(self):
+        return int(self.lib.tpx_service_device_bytes(self.h))
+
     def close(self):
         if self.h:
             self.lib.tpx_service_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """tpx_server: independent request streams in slots admitted against an
+    HBM budget, their runs spread over several HIP streams."""
+
+    def __init__(self, budget_bytes, n_streams=4, params=None, **kw):
+        self.torch = _torch()
+        self.lib = load()
+        self.p = params or make_params(**kw)
+        self.h = ctypes.c_void_p()
+        _check(self.lib.tpx_server_create(ctypes.byref(self.p), int(budget_bytes), int(n_streams),
+                                          ctypes.byref(self.h)), "tpx_server_create")
+
+    def open(self, max_batch_pkts, ring_pkts=None, params=None, **kw):
+        """A new slot (its own parameters, e.g. initial epochs, or the
+        server's): (slot number, its device bytes)."""
+        slot, nb = ctypes.c_uint32(), ctypes.c_size_t()
+        ring = 4 * max_batch_pkts if ring_pkts is None else ring_pkts
+        p = params or (make_params(**kw) if kw else None)
+        _check(self.lib.tpx_server_open(self.h, ctypes.byref(p) if p is not None else None,
+                                        max_batch_pkts, ring, ctypes.byref(slot),
+                                        ctypes.byref(nb)), "tpx_server_open")
+        return int(slot.value), int(nb.value)
+
+    def submit(self, slot, chunk):
+        """Admit a host chunk (numpy uint64) into the slot."""
+        arr = np.ascontiguousarray(np.asarray(chunk).view(np.uint64))
+        seq = ctypes.c_uint64()
+        _check(self.lib.tpx_server_submit(self.h, slot, ctypes.c_void_p(arr.ctypes.data), arr.size,
+                                          0, ctypes.byref(seq), None), "tpx_server_submit")
+        return int(seq.value)
+
+    def run(self, slot, flush=False, hit_cap=1 << 20):
+        """One batch of the slot on its HIP stream: (hits, chunks done)."""
+        torch = self.torch
+        hits = torch.empty((max(hit_cap, 1), 48), dtype=torch.uint8, device="cuda")
+        nh, nd = ctypes.c_size_t(), ctypes.c_uint64()
+        rc = self.lib.tpx_server_run(self.h, slot, int(flush), _ptr(hits), hit_cap,
+                                     ctypes.byref(nh), ctypes.byref(nd), None)
+        if rc == ECAPACITY:
+            raise TpxError(rc, "tpx_server_run", f"need {nh.value} hits")
+        _check(rc, "tpx_server_run")
+        # the run synchronised its own stream: the hits are complete
+        return hits[:nh.value].cpu().numpy().view(HIT_DTYPE).reshape(-1), int(nd.value)
+
+    def close_slot(self, slot):
+        _check(self.lib.tpx_server_close(self.h, slot), "tpx_server_close")
+
+    @property
+    def free_bytes(self):
+        return int(self.lib.tpx_server_free_bytes(self.h))
+
+    def close(self):
+        if self.h:
+            self.lib.tpx_server_destroy(self.h)
             self.h = ctypes.c_void_p()
 
     def __del__(self):

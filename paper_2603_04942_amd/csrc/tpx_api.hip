@@ -568,6 +568,7 @@ struct tpx_stream {
     uint64_t max_chunk;
     uint64_t tab_cap, ev_cap, carry_cap, seg_cap;
     std::vector<void*> allocs;
+    uint64_t device_bytes = 0;  // sum of the allocations
     DevResults* res;
     DevResults* res_h;
     DecodeWs dw;
@@ -630,6 +631,7 @@ tpx_status dalloc(tpx_stream* s, T** p, uint64_t count) {
                     (unsigned long long)(count * sizeof(T)));
     }
     s->allocs.push_back(q);
+    s->device_bytes += std::max<uint64_t>(count, 1) * sizeof(T);
     *p = (T*)q;
     return TPX_OK;
 }
@@ -1124,6 +1126,8 @@ tpx_status tpx_stream_set_segment(tpx_stream* s, uint32_t q) {
 }
 
 uint32_t tpx_stream_get_segment(const tpx_stream* s) { return s ? s->q : 0; }
+
+size_t tpx_stream_device_bytes(const tpx_stream* s) { return s ? (size_t)s->device_bytes : 0; }
 
 int tpx_stream_kernel_count(void) { return fused_variants(); }
 
