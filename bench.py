@@ -102,10 +102,20 @@ def run_gpu(args, wl):
     hits = torch.empty((cap, 48), dtype=torch.uint8, device=dev)
     # clustering kernel and segment stride: the library's autotuner on the
     # workload itself (every kernel at each candidate stride, best of 2)
-    kernels = list(range(-1, tpx.kernel_count()))
-    best_q, best_k, sweep = s.autotune(pk, True, args.c2_strides, hits, cap, reps=2,
-                                       kernels=kernels)
+    # (or the pair given by --kernel / --stride: counter runs, whose timings
+    # the counters distort)
+    if args.kernel is not None or args.stride is not None:
+        if args.kernel is not None:
+            s.set_kernel(args.kernel)
+        if args.stride is not None:
+            s.set_segment(args.stride)
+        best_q, best_k, sweep = s.segment(), s.kernel(), {}
+    else:
+        kernels = list(range(-1, tpx.kernel_count()))
+        best_q, best_k, sweep = s.autotune(pk, True, args.c2_strides, hits, cap, reps=2,
+                                           kernels=kernels)
     tune = dict(stride=best_q, kernel=best_k, kernel_name=tpx.kernel_name(best_k),
+                pinned=not sweep,
                 sweep_ms={f"{tpx.kernel_name(k)} @ {q}": round(v, 4)
                           for (k, q), v in sweep.items()})
     log(f"c2 autotune: {tune}")
@@ -687,6 +697,10 @@ def main():
     ap.add_argument("--strides", type=int, nargs="+",
                     default=[128, 256, 512, 1024, 2048, 4096],
                     help="segment strides the autotuner tries on the uneven-shot workload")
+    ap.add_argument("--kernel", type=int, default=None,
+                    help="pin the clustering kernel of the main step (no autotune)")
+    ap.add_argument("--stride", type=int, default=None,
+                    help="pin the segment stride of the main step (no autotune)")
     ap.add_argument("--c2-strides", type=int, nargs="+", default=[512, 1024, 2048],
                     help="segment strides the autotuner tries on the c2 workload")
     ap.add_argument("--learned-train", type=int, default=10_000_000,
@@ -731,7 +745,9 @@ def main():
     fused = tune["kernel"] >= 0
     sb = stage_bytes(n_pk, n_ev, n_hits, fused)
     dom = max(stages, key=stages.get)
-    kname = FUSED_KERNEL if (fused and dom == "cluster") else STAGE_KERNEL.get(dom, dom)
+    # (the fused kernel by its variant: the traffic summary holds one variant)
+    kname = (f"{FUSED_KERNEL}[{tune['kernel']}]" if (fused and dom == "cluster")
+             else STAGE_KERNEL.get(dom, dom))
     # algorithmic bytes of the method per launch (8 B per packet in, 48 B per
     # hit out: every launch of the dominant kernel serves one whole step)
     path_bytes = 8 * n_pk + HIT_BYTES * n_hits

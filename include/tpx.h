@@ -273,7 +273,7 @@ const char* tpx_stream_stage_name(size_t i);
  * and the workgroup size; tpx_stream_kernel_name names them), or -1 for the
  * staged kernels (components, then moments and hits in a second launch).
  * Other radii always take the staged kernels.  Results do not depend on the
- * kernel.  Default 0.
+ * kernel.  Default 1 (a 256x16 image, 512 threads, eight waves per SIMD).
  *
  * tpx_stream_autotune (the sweep of the uneven-shot workload) runs the chunk
  * at every pair of candidate q (cand_h[n_cand]) and kernel (kern_h[n_kern];
@@ -281,7 +281,8 @@ const char* tpx_stream_stage_name(size_t i);
  * HIP events on `stream`, restoring the stream state before each run and
  * after the last; writes the times to ms_h (host, [n_kern][n_cand], may be
  * NULL) and keeps the fastest pair (*best_h, *best_kern_h, which may be
- * NULL).  hits / hit_cap as in tpx_process_stream; on an error the stream
+ * NULL), except that the pair in force when called, if it is a candidate,
+ * stays unless the fastest beats it by more than 3%.  hits / hit_cap as in tpx_process_stream; on an error the stream
  * keeps its state, its former q and its former kernel. */
 tpx_status tpx_stream_set_segment(tpx_stream* s, uint32_t q);
 uint32_t tpx_stream_get_segment(const tpx_stream* s);
