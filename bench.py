@@ -58,16 +58,20 @@ KERNEL_SOURCES = ("tpx_decode.hip", "tpx_cluster.hip", "tpx_util.hip", "tpx_inte
 
 
 def source_digest():
-    """sha256 over the sources that define and launch the stream path's
-    kernels: HBM traffic counters are only reported while the code they were
-    taken on is unchanged."""
+    """sha256 over the code (comments and blank lines removed) of the sources
+    that define and launch the stream path's kernels: HBM traffic counters are
+    only reported while the code they were taken on is unchanged."""
     import hashlib
+    import re
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2603_04942_amd", "csrc")
     files = [os.path.join(csrc, f) for f in KERNEL_SOURCES]
     for f in files + [os.path.join(ROOT, "include", "tpx.h")]:
-        with open(f, "rb") as fh:
-            h.update(os.path.basename(f).encode() + b"\0" + fh.read())
+        with open(f) as fh:
+            code = re.sub(r"/\*.*?\*/", "", fh.read(), flags=re.S)
+        code = "\n".join(ln.rstrip() for ln in re.sub(r"//[^\n]*", "", code).splitlines()
+                         if ln.strip())
+        h.update(os.path.basename(f).encode() + b"\0" + code.encode())
     return h.hexdigest()
 
 

@@ -319,7 +319,9 @@ tpx_status tpx_stream_autotune(tpx_stream* s, const uint64_t* chunk, size_t n_pk
  *   tpx_service_run     one batch: hits of the shots it closes (all shots when
  *                       flush and the batch holds every admitted chunk) as in
  *                       tpx_process_stream; *n_done_h = chunks processed so
- *                       far.  With nothing admitted it still flushes.  On an
+ *                       far.  With nothing admitted it still flushes; with
+ *                       no chunk ready and no flush it returns at once (no
+ *                       hits, nothing launched).  On an
  *                       error the batch stays admitted.  The batch's copies
  *                       are waited for on the device.  Synchronises `stream`.
  * One host thread may submit while another runs: the admission copies of new
@@ -340,8 +342,8 @@ void tpx_service_destroy(tpx_service* sv);
  *                       (chunk words of the device-resident stream pk[n]) is
  *                       submitted when its last word would have been acquired
  *                       at pkts_per_s packets per second; the calling thread
- *                       runs the service whenever chunks are admitted (flush
- *                       with the last).  lat_ms_h[k] (host, may be NULL) =
+ *                       runs the service whenever admitted chunks are ready
+ *                       (their copies enqueued; flush with the last).  lat_ms_h[k] (host, may be NULL) =
  *                       completion of the run that processed chunk k minus
  *                       its release; *n_chunks_h chunks, *n_runs_h runs.  The
  *                       service must hold no unprocessed chunks.  hits /

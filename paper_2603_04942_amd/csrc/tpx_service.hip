@@ -176,6 +176,14 @@ tpx_status tpx_service_run(tpx_service* sv, int flush, tpx_hit* hits, size_t hit
         }
         last = take == sv->q.size();
     }
+    if (take == 0 && !(flush && last)) {
+        // nothing ready and no end of stream: a call on no words closes nothing
+        *n_hits_h = 0;
+        if (stats_h) *stats_h = tpx_stats{};
+        std::lock_guard<std::mutex> lk(sv->mu);
+        *n_done_h = sv->n_done;
+        return TPX_OK;
+    }
     for (hipEvent_t e : evs)
         if (hipStreamWaitEvent(hs, e, 0) != hipSuccess) return tpx::report(TPX_EHIP, "wait failed");
     const uint64_t n = end - start;
@@ -270,10 +278,11 @@ tpx_status tpx_service_replay(tpx_service* sv, const uint64_t* pk, size_t n, siz
     tpx_status rc = TPX_OK;
     uint64_t runs = 0, done = 0;
     while (rc == TPX_OK && done < n_chunks) {
-        uint64_t admitted;
+        uint64_t admitted;  // chunks processed or ready (copy enqueued), in order
         {
             std::lock_guard<std::mutex> lk(sv->mu);
-            admitted = sv->n_sub - seq0;
+            admitted = sv->n_done - seq0;
+            for (size_t i = 0; i < sv->q.size() && sv->q[i].issued; ++i) ++admitted;
         }
         {
             std::lock_guard<std::mutex> lk(mu);

@@ -427,6 +427,10 @@ hipError_t hipGetDevice(int* d) {
     return hipSuccess;
 }
 hipError_t hipSetDevice(int) { return hipSuccess; }
+hipError_t hipDeviceGetAttribute(int* v, int attr, int) {
+    *v = attr == hipDeviceAttributeMultiprocessorCount ? 3 : 0;
+    return hipSuccess;
+}
 const char* hipGetErrorString(hipError_t) { return "hip error (emulation)"; }
 
 // ------------------------------------------------------------ C entry points

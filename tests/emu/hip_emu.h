@@ -40,6 +40,8 @@
 #define __host__
 #define __forceinline__ inline
 #define __launch_bounds__(...)
+// per-kernel occupancy hints of the AMDGPU back end: nothing to emulate
+#define amdgpu_waves_per_eu(...)
 #define __shared__ static
 
 // ------------------------------------------------------------ vector types
@@ -328,6 +330,9 @@ hipError_t hipPeekAtLastError();
 hipError_t hipDeviceSynchronize();
 hipError_t hipGetDevice(int* d);
 hipError_t hipSetDevice(int d);
+enum { hipDeviceAttributeMultiprocessorCount = 1 };
+// a small device: persistent grids take several work items per workgroup
+hipError_t hipDeviceGetAttribute(int* v, int attr, int dev);
 // a file-scope device array is an ordinary host array here: its symbol is
 // its address
 #define HIP_SYMBOL(x) ((const void*)&(x))
