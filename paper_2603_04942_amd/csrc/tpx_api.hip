@@ -592,6 +592,8 @@ struct tpx_stream {
     uint32_t *shot_stage, *tile_cnt, *tile_lo, *tile_hi, *tile_off;
     unsigned long long* tile_stat;
     uint32_t* hit_index;    // hit of every event of the last call (when kept)
+    uint32_t* defer;        // routed kernel: segments left to its persistent launch
+    uint32_t n_cu;          // compute units of the device (persistent grid)
     // committed host state
     int64_t pix_epoch, tdc_epoch;
     uint64_t pix_last, tdc_last;
@@ -710,7 +712,7 @@ void stream_cluster(tpx_stream* s, const ClusterArgs& c, uint64_t grid, hipStrea
     s->last_fused = use_fused(s);
     if (s->last_fused) {
         mark(s, 4, hs);
-        launch_cluster_fused(c, grid, s->kernel, hs);
+        launch_cluster_fused(c, grid, s->kernel, s->defer, s->n_cu, hs);
         mark(s, 5, hs);
         launch_scan_u32(s->seg_cnt, s->seg_off, 0, &s->res->n_seg, s->block_tmp, hs);
         launch_hit_compact(c, grid, hs);
@@ -919,7 +921,18 @@ tpx_status tpx_stream_create(const tpx_params* p_h, size_t max_chunk_pkts, tpx_s
     ALLOC(s->g_acc, 8 * s->ev_cap);
     ALLOC(s->hits_tmp, s->ev_cap);
     ALLOC(s->hit_index, s->ev_cap);
+    ALLOC(s->defer, s->seg_cap);
 #undef ALLOC
+    {
+        int dev = 0, cu = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            cu <= 0) {
+            (void)hipGetLastError();
+            cu = 256;
+        }
+        s->n_cu = (uint32_t)cu;
+    }
     s->pix_epoch = p_h->pix_epoch0;
     s->tdc_epoch = p_h->tdc_epoch0;
     *out_h = s;

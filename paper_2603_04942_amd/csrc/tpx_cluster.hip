@@ -1228,11 +1228,14 @@ namespace tpx {
 //
 // Phases (each ends at a workgroup barrier reached by every thread):
 //   1. load + push on the slot lists;
-//   2. each event unites with its neighbours in the backward half of its box
-//      (the row above, the slot to its left, and earlier events of its own
-//      slot), so every edge is seen once; lock-free union-find that hooks
-//      the larger root under the smaller by compare-and-swap;
-//   3. final roots (the smallest position of each component = its label);
+//   2. each event finds its neighbours in the backward half of its box (the
+//      row above, the slot to its left, and earlier events of its own slot),
+//      so every edge is seen once, keeps up to 8 of them in registers and
+//      lowers the parents of both ends to the smaller end (LDS atomic
+//      minimum): a min-neighbour forest;
+//   3. rounds of pointer jumping and root hooking over the kept edges until
+//      no edge joins two trees (the smallest position of each component, its
+//      label, is then every member's parent);
 //   4. ranks of the roots in position order;
 //   5. moments per component (LDS atomics);
 //   6. hits, staged.
@@ -1247,6 +1250,9 @@ struct FusedCfg {
     static constexpr int kYHB = 8 - kYB;           // bits of y above the slot's
     static constexpr int kGShift = 16 + kYHB;      // group start above the time and y bits
     static constexpr int kE = kSeg / kNT;          // events per thread
+    // edges kept in registers per event (more are found again by walking the
+    // slot lists in every round): fewer where a thread holds many events
+    static constexpr int kEdges = kE > 4 ? 4 : 8;
     static constexpr int kNW = kNT / 64;
     static constexpr int kOffKey = kSlots * 2;         // u32[kSeg]
     static constexpr int kOffPar = kOffKey + 4 * kSeg; // u32[kSeg]
@@ -1381,14 +1387,15 @@ __device__ uint32_t fused_big(const ClusterArgs& a, uint8_t* lds, uint32_t* scan
 }
 
 // kWaves: waves per SIMD the register allocation must allow (0: no bound)
-template <int kYB, int kNT, int kSeg, int kWaves = 0>
-__global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(kWaves ? kWaves : 1)))
-void k_cluster_fused(ClusterArgs a) {
+// Segment k in one workgroup (every return below is taken by the whole
+// workgroup).  With `defer`, a segment beyond the LDS capacity is not
+// clustered here: its index is appended to a.defer_list for a later launch
+// of a larger configuration.
+template <int kYB, int kNT, int kSeg>
+__device__ __forceinline__ void fused_segment(const ClusterArgs& a, uint32_t k, bool defer,
+                                              uint8_t* lds, uint32_t* scan_tmp, uint32_t* goff) {
     using C = FusedCfg<kYB, kNT, kSeg>;
     constexpr int kE = C::kE;
-    __shared__ __attribute__((aligned(16))) uint8_t lds[C::kBytes];
-    __shared__ uint32_t scan_tmp[C::kNW + 1];
-    __shared__ uint32_t goff[kNT + 1];
     uint32_t* img = (uint32_t*)lds;  // as 32-bit words: two u16 heads each
     const uint16_t* head16 = (const uint16_t*)lds;
     uint32_t* key = (uint32_t*)(lds + C::kOffKey);
@@ -1406,7 +1413,6 @@ void k_cluster_fused(ClusterArgs a) {
 
     const int tid = threadIdx.x;
     unsigned long long* err = &a.res->err;
-    const uint32_t k = blockIdx.x;
     const uint64_t N = n_events(a);
     const uint64_t n_seg = (N + a.q - 1) / a.q;
     if (k >= n_seg) return;
@@ -1419,6 +1425,10 @@ void k_cluster_fused(ClusterArgs a) {
     const uint64_t e0 = sg.e0;
     if (n == 0) {
         if (tid == 0) a.seg_cnt[k] = 0;
+        return;
+    }
+    if (defer && n > (uint32_t)kSeg) {
+        if (tid == 0) a.defer_list[atomicAdd(&a.res->aux_ticket, 1ull)] = k;
         return;
     }
     const uint32_t ng = sg.g_hi - sg.g_lo;
@@ -1480,15 +1490,17 @@ void k_cluster_fused(ClusterArgs a) {
         // longer lists are walked afterwards).  Every event's parent becomes
         // the smallest of itself and its neighbours (atomic minimum from both
         // ends of each edge): a forest whose trees are mostly whole already.
-        // The edges (up to 8 per event) stay in registers.
-        uint32_t nb[kE][4];
-        uint32_t meta[kE];  // edges kept (bits 0-7), live edges (8-15)
+        // The edges (up to C::kEdges per event) stay in registers.
+        constexpr int kEd = C::kEdges, kNbW = kEd / 2;
+        uint32_t nb[kE][kNbW];
+        uint32_t meta[kE];  // edges found (bits 0-7), live kept edges (8-15)
         bool ok = true;
 #pragma unroll
         for (int q = 0; q < kE; ++q) {
             const uint32_t i = tid + q * kNT;
             meta[q] = 0;
-            nb[q][0] = nb[q][1] = nb[q][2] = nb[q][3] = 0;
+#pragma unroll
+            for (int w = 0; w < kNbW; ++w) nb[q][w] = 0;
             if (i >= n) continue;
             const uint32_t xy = xyt[i];
             const int x = (int)(xy & 255u), y = (int)((xy >> 8) & 255u);
@@ -1525,12 +1537,10 @@ void k_cluster_fused(ClusterArgs a) {
                     absdiff(kj & 0xFFFFu, ti) <= dt) {
                     if (j < m) m = j;
                     if (j > i) atomicMin(par + j, i);
-                    const uint32_t wd = (c >> 1) & 3u, sh16 = (c & 1u) * 16u;
-                    if (c < 8) {
-                        nb[q][0] |= wd == 0 ? j << sh16 : 0u;
-                        nb[q][1] |= wd == 1 ? j << sh16 : 0u;
-                        nb[q][2] |= wd == 2 ? j << sh16 : 0u;
-                        nb[q][3] |= wd == 3 ? j << sh16 : 0u;
+                    const uint32_t wd = c >> 1, sh16 = (c & 1u) * 16u;
+                    if (c < (uint32_t)kEd) {
+#pragma unroll
+                        for (int w = 0; w < kNbW; ++w) nb[q][w] |= wd == (uint32_t)w ? j << sh16 : 0u;
                     }
                     ++c;
                 }
@@ -1556,7 +1566,8 @@ void k_cluster_fused(ClusterArgs a) {
                     }
                 }
             }
-            meta[q] = (c < 255 ? c : 255) | ((c > 8 ? 0xFFu : (1u << c) - 1u) << 8);
+            meta[q] = (c < 255 ? c : 255) |
+                      ((c > (uint32_t)kEd ? (1u << kEd) - 1u : (1u << c) - 1u) << 8);
             if (m < i) atomicMin(par + i, m);
         }
         if (!ok) atomicOr(err, (unsigned long long)kErrLoopChain);
@@ -1566,8 +1577,8 @@ void k_cluster_fused(ClusterArgs a) {
         // larger root is pointed at the smaller (atomic minimum: parents only
         // ever decrease, so the forest stays a forest); an edge once inside
         // a tree stays inside and is dropped.  A round with no such edge
-        // ends it.  An event with more than 8 smaller neighbours walks its
-        // lists in every round.
+        // ends it.  An event with more edges than it keeps walks its lists in
+        // every round.
         for (uint32_t round = 0;; ++round) {
 #pragma unroll
             for (int q = 0; q < kE; ++q) {
@@ -1583,16 +1594,16 @@ void k_cluster_fused(ClusterArgs a) {
             for (int q = 0; q < kE; ++q) {
                 const uint32_t i = tid + q * kNT;
                 const uint32_t cq = meta[q] & 0xFFu;
-                if (i >= n || ((meta[q] >> 8) == 0 && cq <= 8)) continue;
+                if (i >= n || ((meta[q] >> 8) == 0 && cq <= (uint32_t)kEd)) continue;
                 const uint32_t ri = ald(par + i);
-                uint32_t rj[8];
+                uint32_t rj[kEd];
 #pragma unroll
-                for (int t = 0; t < 8; ++t) {
+                for (int t = 0; t < kEd; ++t) {
                     const uint32_t j = (nb[q][t >> 1] >> ((t & 1) * 16)) & 0xFFFFu;
                     rj[t] = (meta[q] >> (8 + t)) & 1u ? ald(par + j) : ri;
                 }
 #pragma unroll
-                for (int t = 0; t < 8; ++t) {
+                for (int t = 0; t < kEd; ++t) {
                     if (rj[t] == ri) {
                         meta[q] &= ~(1u << (8 + t));
                     } else {
@@ -1601,7 +1612,7 @@ void k_cluster_fused(ClusterArgs a) {
                         hooked = true;
                     }
                 }
-                if (cq > 8) {
+                if (cq > (uint32_t)kEd) {
                     const uint32_t xy = xyt[i];
                     const int x = (int)(xy & 255u), y = (int)((xy >> 8) & 255u);
                     const uint32_t ki = key[i];
@@ -1765,6 +1776,43 @@ void k_cluster_fused(ClusterArgs a) {
     }
 }
 
+// one workgroup per segment; with a.defer_list, segments beyond kSeg events
+// are left to k_cluster_fused_list
+template <int kYB, int kNT, int kSeg, int kWaves = 0>
+__global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(kWaves ? kWaves : 1)))
+void k_cluster_fused(ClusterArgs a) {
+    using C = FusedCfg<kYB, kNT, kSeg>;
+    __shared__ __attribute__((aligned(16))) uint8_t lds[C::kBytes];
+    __shared__ uint32_t scan_tmp[C::kNW + 1];
+    __shared__ uint32_t goff[kNT + 1];
+    fused_segment<kYB, kNT, kSeg>(a, blockIdx.x, a.defer_list != nullptr, lds, scan_tmp, goff);
+}
+
+// Persistent grid over the segments a previous k_cluster_fused launch
+// deferred (a.res->aux_ticket of them in a.defer_list): each workgroup takes
+// the next list entry from a ticket counter until the list is exhausted.  The
+// ticket is broadcast through LDS between two barriers, so every thread of
+// the workgroup leaves the loop in the same iteration; no workgroup waits for
+// another.
+template <int kYB, int kNT, int kSeg>
+__global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(kNT / 256)))
+void k_cluster_fused_list(ClusterArgs a) {
+    using C = FusedCfg<kYB, kNT, kSeg>;
+    __shared__ __attribute__((aligned(16))) uint8_t lds[C::kBytes];
+    __shared__ uint32_t scan_tmp[C::kNW + 1];
+    __shared__ uint32_t goff[kNT + 1];
+    __shared__ unsigned long long ticket;
+    const unsigned long long n_list = a.res->aux_ticket;  // final: the deferring launch is done
+    for (;;) {
+        if (threadIdx.x == 0) ticket = atomicAdd(&a.res->seg_ticket, 1ull);
+        __syncthreads();
+        const unsigned long long t = ticket;
+        if (t >= n_list) break;
+        fused_segment<kYB, kNT, kSeg>(a, a.defer_list[t], false, lds, scan_tmp, goff);
+        __syncthreads();  // LDS and the ticket are reused by the next segment
+    }
+}
+
 // Staged hits to their final place: one wave per segment copies its hits
 // (8-byte words: a hit record is 8-byte aligned) from the segment's staging
 // range to seg_off[k]; with a hit index, the segment's events get their final
@@ -1801,6 +1849,8 @@ static const FusedVariant kFusedVariants[] = {
     {"image 256x64, 512 threads, 2048 events in LDS"},
     {"image 256x32, 1024 threads, 2048 events in LDS"},
     {"image 256x64, 1024 threads, 8192 events in LDS"},
+    {"routed: segments up to 2048 events as variant 1, larger ones by a persistent grid of "
+     "variant 4's configuration"},
 };
 
 int fused_variants() { return (int)(sizeof(kFusedVariants) / sizeof(kFusedVariants[0])); }
@@ -1808,9 +1858,19 @@ const char* fused_variant_name(int v) {
     return v >= 0 && v < fused_variants() ? kFusedVariants[v].name : "?";
 }
 
-void launch_cluster_fused(const ClusterArgs& a, uint64_t grid, int variant, hipStream_t s) {
+void launch_cluster_fused(const ClusterArgs& a0, uint64_t grid, int variant, uint32_t* defer_list,
+                          uint32_t list_grid, hipStream_t s) {
     if (grid == 0) return;
     const dim3 g((unsigned)grid);
+    ClusterArgs a = a0;
+    a.defer_list = nullptr;
+    if (variant == 5) {
+        a.defer_list = defer_list;
+        hipLaunchKernelGGL((k_cluster_fused<4, 512, 2048, 8>), g, dim3(512), 0, s, a);
+        hipLaunchKernelGGL((k_cluster_fused_list<6, 1024, 8192>), dim3(list_grid ? list_grid : 1),
+                           dim3(1024), 0, s, a);
+        return;
+    }
     switch (variant) {
     case 1: hipLaunchKernelGGL((k_cluster_fused<4, 512, 2048, 8>), g, dim3(512), 0, s, a); break;
     case 2: hipLaunchKernelGGL((k_cluster_fused<6, 512, 2048>), g, dim3(512), 0, s, a); break;

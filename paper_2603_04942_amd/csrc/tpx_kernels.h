@@ -67,6 +67,7 @@ struct ClusterArgs {
     // fused stream kernel (launch_cluster_fused)
     tpx_hit* hits_tmp;         // staging: hit r of a segment at its first event + r
     uint32_t* hit_index;       // optional: hit of every event (call-relative), or null
+    uint32_t* defer_list;      // routed variant: segments left to the persistent launch
 };
 
 void launch_tile_summary(const uint64_t* pk, uint64_t n, uint32_t sub, uint64_t jump,
@@ -102,10 +103,15 @@ void launch_seg_centroid(const ClusterArgs& a, uint64_t grid, hipStream_t s);
 // stream mode, radius 1, times of flight below 2^16: components, moments and
 // hits of every segment in one launch, hits staged at each segment's own
 // range of a.hits_tmp and its component count in seg_cnt; `variant` selects
-// the image height, workgroup size and LDS capacity (fused_variants()).
+// the image height, workgroup size and LDS capacity (fused_variants()); the
+// routed variant clusters segments beyond 2,048 events in a second,
+// persistent launch of list_grid workgroups over the segments the first one
+// appended to defer_list (one entry per segment: grid words; the counters
+// res->aux_ticket and res->seg_ticket must be zero).
 // Then a prefix sum of seg_cnt into seg_off, and launch_hit_compact moves the
 // hits to their final place (and sets res->n_hits).
-void launch_cluster_fused(const ClusterArgs& a, uint64_t grid, int variant, hipStream_t s);
+void launch_cluster_fused(const ClusterArgs& a, uint64_t grid, int variant, uint32_t* defer_list,
+                          uint32_t list_grid, hipStream_t s);
 void launch_hit_compact(const ClusterArgs& a, uint64_t grid, hipStream_t s);
 int fused_variants();
 const char* fused_variant_name(int variant);

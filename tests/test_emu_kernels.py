@@ -89,13 +89,14 @@ def _assert_hits(hits, ref):
     assert np.abs(hits["tof_ns"] - ref["tof_ns"]).max(initial=0) <= 0.1
 
 
-@pytest.mark.parametrize("kernel", [-1, 0, 1, 2, 3, 4])
+@pytest.mark.parametrize("kernel", [-1, 0, 1, 2, 3, 4, 5])
 @pytest.mark.parametrize("name,shots,chunk", [("c1", 30, 1500), ("c3", 25, 30000)])
 def test_stream_kernels(emu, orc, kernel, name, shots, chunk):
     """Every clustering kernel of the stream path (the staged pair and each
-    fused variant: ticketed segments, slot lists, unions, moments, look-back
-    over segments) on the small and the uneven-shot workloads, whole and in
-    chunks."""
+    fused variant: slot lists, forest and hook rounds, moments, staged hits
+    and their compaction; the routed variant's deferred segments and its
+    persistent launch) on the small and the uneven-shot workloads, whole and
+    in chunks."""
     w = synth.make_config(name, n_shots=shots)
     kw = dict(pix_epoch0=w.pix_epoch0, tdc_epoch0=w.tdc_epoch0)
     ref, _ = orc.run(w.packets, **kw)
@@ -107,16 +108,20 @@ def test_stream_kernels(emu, orc, kernel, name, shots, chunk):
         _assert_hits(hits, ref)
 
 
-@pytest.mark.parametrize("kernel", [0, 4])
-@pytest.mark.parametrize("case", ["iso1500", "iso3000", "square"])
+@pytest.mark.parametrize("kernel,case", [(k, c) for k in (0, 4, 5)
+                                         for c in ("iso1500", "iso3000", "square")]
+                         + [(5, "iso9000")])
 def test_stream_fused_capacity_paths(emu, orc, kernel, case):
     """The fused kernel's fallbacks: more components than the LDS
     accumulators hold (1,500 isolated pixels), a segment beyond the LDS event
-    capacity (3,000; global-memory lists and unions), and one component of
-    7,200 pixels at ToT 1023 (moments of a large segment)."""
+    capacity (3,000; global-memory lists and unions, or the routed variant's
+    persistent launch), one component of 7,200 pixels at ToT 1023 (moments
+    of a large segment), and for the routed variant a segment beyond its
+    persistent launch's 8,192 events (9,000 isolated pixels)."""
     from cases import big_component_packets, many_components_packets
     pk = {"iso1500": lambda: many_components_packets(1500),
           "iso3000": lambda: many_components_packets(3000),
+          "iso9000": lambda: many_components_packets(9000),
           "square": lambda: big_component_packets(side=60, layers=2)}[case]()
     ref, _ = orc.run(pk)
     st, hits, errs = emu.run_stream(pk, 1 << 22, kernel=kernel, preempt=100, seed=5)
