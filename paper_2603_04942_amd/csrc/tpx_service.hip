@@ -11,6 +11,7 @@
 // the chunk on the service's own stream and records an event; a run makes its
 // stream wait for the events of the chunks it takes, on the device.
 #include <chrono>
+#include <condition_variable>
 #include <deque>
 #include <mutex>
 #include <thread>
@@ -238,8 +239,9 @@ tpx_status tpx_service_replay(tpx_service* sv, const uint64_t* pk, size_t n, siz
     if (lat_ms_h && lat_cap < n_chunks) return tpx::report(TPX_EINVAL, "lat_cap too small");
     using clk = std::chrono::steady_clock;
     std::vector<clk::time_point> rel(n_chunks);
-    std::vector<int> released(n_chunks, 0);
-    std::mutex mu;
+    std::mutex mu;                // guards rel, issued, prod_rc
+    std::condition_variable cv;   // the producer admitted a chunk or failed
+    uint64_t issued = 0;          // chunks submitted (copies enqueued), in order
     tpx_status prod_rc = TPX_OK;
     uint64_t seq0 = 0;
     {
@@ -266,31 +268,26 @@ tpx_status tpx_service_replay(tpx_service* sv, const uint64_t* pk, size_t n, siz
                 if (rc != TPX_ECAPACITY) break;
                 std::this_thread::yield();
             }
-            std::lock_guard<std::mutex> lk(mu);
-            rel[k] = due < r ? due : r;
-            released[k] = 1;
-            if (rc != TPX_OK) {
-                prod_rc = rc;
-                return;
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                rel[k] = due < r ? due : r;
+                if (rc != TPX_OK) prod_rc = rc;
+                else issued = k + 1;
             }
+            cv.notify_one();
+            if (rc != TPX_OK) return;
         }
     });
     tpx_status rc = TPX_OK;
     uint64_t runs = 0, done = 0;
     while (rc == TPX_OK && done < n_chunks) {
-        uint64_t admitted;  // chunks processed or ready (copy enqueued), in order
+        uint64_t admitted;  // chunks whose copies are enqueued
         {
-            std::lock_guard<std::mutex> lk(sv->mu);
-            admitted = sv->n_done - seq0;
-            for (size_t i = 0; i < sv->q.size() && sv->q[i].issued; ++i) ++admitted;
-        }
-        {
-            std::lock_guard<std::mutex> lk(mu);
+            // sleep until the producer admits a chunk not yet processed
+            std::unique_lock<std::mutex> lk(mu);
+            cv.wait(lk, [&] { return issued > done || prod_rc != TPX_OK; });
             if (prod_rc != TPX_OK) break;
-        }
-        if (admitted == done) {
-            std::this_thread::yield();
-            continue;
+            admitted = issued;
         }
         size_t nh = 0;
         uint64_t n_done = 0;
