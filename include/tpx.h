@@ -292,6 +292,22 @@ int tpx_stream_kernel_count(void);
 const char* tpx_stream_kernel_name(int k);
 tpx_status tpx_stream_set_kernel(tpx_stream* s, int k);
 int tpx_stream_get_kernel(const tpx_stream* s);
+/* Persistent launch of small chunks (batching over triggers, Sec. VI, in one
+ * launch): a chunk of at most max_tiles tiles of 4,096 words (0 <= max_tiles
+ * <= 512; default 4) that takes the fused clustering kernel runs the whole
+ * fast path -- decode, unwrap, shot assignment, grouping, components,
+ * moments, hits, carry -- as one launch of a persistent grid whose
+ * workgroups take work items (tiles, the prefix over tiles, segments, ...)
+ * from a ticket counter in dependency order; inside it, segments are
+ * clustered by the 2,048-event configuration of variant 1 whatever the
+ * stream's variant (larger segments keep their arrays in global scratch).
+ * Results do not depend on the setting.  Larger chunks, the staged kernels
+ * and chunks whose events are out of shot order take the separate launches.
+ * The stage clock reports such a call's whole launch as its cluster stage.
+ * set: TPX_EINVAL outside the range; get returns the limit, or -1 for a
+ * NULL stream. */
+tpx_status tpx_stream_set_persistent(tpx_stream* s, int max_tiles);
+int tpx_stream_get_persistent(const tpx_stream* s);
 tpx_status tpx_stream_autotune(tpx_stream* s, const uint64_t* chunk, size_t n_pkts, int flush,
                                tpx_hit* hits, size_t hit_cap, const uint32_t* cand_h,
                                size_t n_cand, const int* kern_h, size_t n_kern, int reps,

@@ -75,7 +75,8 @@ EXPORTS = ("tpx_params_default", "tpx_unwrap_state_init", "tpx_workspace_bytes",
            "tpx_stream_set_segment", "tpx_stream_get_segment", "tpx_stream_autotune",
            "tpx_stream_patch_workspace_bytes", "tpx_stream_patches", "tpx_stream_set_patches",
            "tpx_stream_kernel_count", "tpx_stream_kernel_name", "tpx_stream_set_kernel",
-           "tpx_stream_get_kernel", "tpx_cluster_static", "tpx_cluster_static_max_events",
+           "tpx_stream_get_kernel", "tpx_stream_set_persistent", "tpx_stream_get_persistent",
+           "tpx_cluster_static", "tpx_cluster_static_max_events",
            "tpx_walk_fit", "tpx_walk_fit_workspace_bytes", "tpx_stream_device_bytes",
            "tpx_service_device_bytes", "tpx_service_replay", "tpx_server_create", "tpx_server_open",
            "tpx_server_submit", "tpx_server_run", "tpx_server_close", "tpx_server_free_bytes",
@@ -170,6 +171,10 @@ def load(path=LIB_PATH):
     lib.tpx_stream_set_kernel.restype = I
     lib.tpx_stream_get_kernel.argtypes = [P]
     lib.tpx_stream_get_kernel.restype = ctypes.c_int
+    lib.tpx_stream_set_persistent.argtypes = [P, ctypes.c_int]
+    lib.tpx_stream_set_persistent.restype = I
+    lib.tpx_stream_get_persistent.argtypes = [P]
+    lib.tpx_stream_get_persistent.restype = ctypes.c_int
     lib.tpx_stream_set_patches.argtypes = [P, ctypes.c_int]
     lib.tpx_stream_set_patches.restype = I
     lib.tpx_stream_patch_workspace_bytes.argtypes = [S]
@@ -382,7 +387,8 @@ class Stream:
     kernel: clustering kernel (None = the library's default); patches: record
     the hit of every event so that patches() can follow each call."""
 
-    def __init__(self, max_chunk_pkts, params=None, kernel=None, patches=False, **kw):
+    def __init__(self, max_chunk_pkts, params=None, kernel=None, patches=False, persistent=None,
+                 **kw):
         self.torch = _torch()
         self.lib = load()
         self.params = params or make_params(**kw)
@@ -394,6 +400,8 @@ class Stream:
         self.max_chunk = max_chunk_pkts
         if kernel is not None:
             self.set_kernel(kernel)
+        if persistent is not None:
+            self.set_persistent(persistent)
         if patches:
             self.set_patches(True)
 
@@ -448,6 +456,18 @@ class Stream:
 
     def kernel(self):
         return int(self.lib.tpx_stream_get_kernel(self.h))
+
+    def set_persistent(self, max_tiles=512):
+        """Chunks of at most max_tiles tiles (4,096 words each) in one
+        persistent launch; True = every chunk the launch can take (512
+        tiles), False = none."""
+        if max_tiles is True:
+            max_tiles = 512
+        _check(self.lib.tpx_stream_set_persistent(self.h, int(max_tiles)),
+               "tpx_stream_set_persistent")
+
+    def persistent(self):
+        return int(self.lib.tpx_stream_get_persistent(self.h))
 
     def autotune(self, chunk, flush, candidates, hits, hit_cap, reps=3, kernels=None):
         """tpx_stream_autotune over strides x kernels (None: the current
@@ -640,9 +660,9 @@ class Server:
             pass
 
 
-def process_stream(packets, flush=True, kernel=None, **kw):
+def process_stream(packets, flush=True, kernel=None, persistent=None, **kw):
     """One-shot helper: the whole packet buffer as a single flushed chunk."""
-    s = Stream(max(int(len(packets)), 1), kernel=kernel, **kw)
+    s = Stream(max(int(len(packets)), 1), kernel=kernel, persistent=persistent, **kw)
     try:
         return s.process(packets, flush=flush)
     finally:

@@ -26,7 +26,8 @@
 // per component and writes one hit per component at its final position, so no
 // segment ever waits for another.  Segments larger than the LDS capacity take
 // the same steps with their per-event arrays in global memory.
-#include "tpx_kernels.h"
+#include "tpx_decode_dev.h"
+#include "tpx_util_dev.h"
 
 namespace tpx {
 
@@ -622,22 +623,30 @@ __device__ void seg_big(const ClusterArgs& a, uint8_t* lds, uint32_t* scan_tmp, 
 // Segment table: seg_lo[k] = first group whose first event is at or after
 // k q, for k = 0..n_seg (n_seg = ceil(N / q)).  One thread per group g = 0..G
 // fills the k in (grp_off[g-1] / q, grp_off[g] / q]; g = G closes at n_seg.
-__global__ void k_seg_table(const uint32_t* __restrict__ grp_off, const unsigned long long* n_grp_dev,
-                            const unsigned long long* n_ev_dev, const unsigned long long* skip,
-                            uint32_t q, uint32_t* seg_lo, DevResults* res) {
+__device__ __forceinline__ void seg_table_range(const uint32_t* __restrict__ grp_off,
+                                const unsigned long long* n_grp_dev,
+                                const unsigned long long* n_ev_dev, const unsigned long long* skip,
+                                uint32_t q, uint32_t* seg_lo, DevResults* res, uint64_t first,
+                                uint64_t stride) {
     const bool sk = skip && *skip;
     const uint64_t G = *n_grp_dev, N = sk ? 0 : *n_ev_dev;
     const uint64_t n_seg = (N + q - 1) / q;
-    if (blockIdx.x == 0 && threadIdx.x == 0) res->n_seg = n_seg;
+    if (first == 0) res->n_seg = n_seg;
     if (sk) return;
-    for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g <= G;
-         g += (uint64_t)gridDim.x * blockDim.x) {
+    for (uint64_t g = first; g <= G; g += stride) {
         // offsets never exceed N in a valid table; the clamps keep every
         // write inside seg_lo[0..n_seg] whatever the table holds
         const int64_t k_prev = g == 0 ? -1 : (int64_t)min<uint64_t>(grp_off[g - 1] / q, n_seg);
         const int64_t k_hi = g == G ? (int64_t)n_seg : (int64_t)min<uint64_t>(grp_off[g] / q, n_seg);
         for (int64_t k = k_prev + 1; k <= k_hi; ++k) seg_lo[k] = (uint32_t)g;
     }
+}
+__global__ void k_seg_table(const uint32_t* __restrict__ grp_off, const unsigned long long* n_grp_dev,
+                            const unsigned long long* n_ev_dev, const unsigned long long* skip,
+                            uint32_t q, uint32_t* seg_lo, DevResults* res) {
+    seg_table_range(grp_off, n_grp_dev, n_ev_dev, skip, q, seg_lo, res,
+                    (uint64_t)blockIdx.x * blockDim.x + threadIdx.x,
+                    (uint64_t)gridDim.x * blockDim.x);
 }
 
 void launch_seg_table(const uint32_t* grp_off, const unsigned long long* n_grp_dev,
@@ -1319,7 +1328,7 @@ __device__ inline void fused_emit(const ClusterArgs& a, const Seg& sg, const uin
 // global scratch, the image in LDS.  Leaves the rank of every event's
 // component in a.rank[e0 + i] and returns the component count.
 template <class C, int kNT>
-__device__ uint32_t fused_big(const ClusterArgs& a, uint8_t* lds, uint32_t* scan_tmp,
+__device__ __forceinline__ uint32_t fused_big(const ClusterArgs& a, uint8_t* lds, uint32_t* scan_tmp,
                               const uint32_t* goff, bool goff_lds, const Seg& sg) {
     uint32_t* img = (uint32_t*)lds;
     const uint64_t e0 = sg.e0;
@@ -1818,12 +1827,12 @@ void k_cluster_fused_list(ClusterArgs a) {
 // range to seg_off[k]; with a hit index, the segment's events get their final
 // hit.
 constexpr int kCompactWG = 256;
-__global__ __launch_bounds__(kCompactWG) void k_hit_compact(ClusterArgs a) {
+// segment k by one wave (k = 0 also records the hit count)
+__device__ __forceinline__ void hit_compact_wave(const ClusterArgs& a, uint64_t k) {
     const uint64_t N = n_events(a);
     const uint64_t n_seg = (N + a.q - 1) / a.q;
-    if (blockIdx.x == 0 && threadIdx.x == 0) a.res->n_hits = a.seg_off[n_seg];
     const int lane = (int)__lane_id();
-    const uint64_t k = (uint64_t)blockIdx.x * (kCompactWG / 64) + (threadIdx.x >> 6);
+    if (k == 0 && lane == 0) a.res->n_hits = a.seg_off[n_seg];
     if (k >= n_seg) return;
     const uint32_t g_lo = a.seg_lo[k], g_hi = a.seg_lo[k + 1];
     const uint64_t e0 = a.grp_off[g_lo], e1 = a.grp_off[g_hi];
@@ -1838,6 +1847,9 @@ __global__ __launch_bounds__(kCompactWG) void k_hit_compact(ClusterArgs a) {
     for (uint64_t w = lane; w < words; w += 64) dst[w] = src[w];
     if (a.hit_index)
         for (uint64_t i = e0 + lane; i < e1; i += 64) a.hit_index[i] += (uint32_t)off;
+}
+__global__ __launch_bounds__(kCompactWG) void k_hit_compact(ClusterArgs a) {
+    hit_compact_wave(a, (uint64_t)blockIdx.x * (kCompactWG / 64) + (threadIdx.x >> 6));
 }
 
 struct FusedVariant {
@@ -1884,6 +1896,286 @@ void launch_hit_compact(const ClusterArgs& a, uint64_t grid, hipStream_t s) {
     if (grid == 0) return;
     const uint64_t blocks = (grid + kCompactWG / 64 - 1) / (kCompactWG / 64);
     hipLaunchKernelGGL(k_hit_compact, dim3((unsigned)blocks), dim3(kCompactWG), 0, s, a);
+}
+
+}  // namespace tpx
+
+namespace tpx {
+
+// ============================================== persistent chunk kernel
+// One launch for the whole fast stream path of a chunk (decode, unwrap,
+// shot assignment and compaction, grouping, components, moments, hits,
+// carry): a persistent grid whose workgroups take work items from a ticket
+// counter.  Items are numbered in dependency order, and an item waits only
+// for the done-counters of items with smaller tickets, which are held by
+// workgroups that are already running; so the grid needs no co-residency and
+// every wait ends (each one is also bounded).  Every item waits for each
+// item it reads from directly (not only through a chain that an empty range
+// of items would break, as with a chunk of no tiles).  Items:
+//   [0, T)        tile summaries                       -> kDoneSum
+//   T             prefix over the tiles (one workgroup: entry states,
+//                 trigger unwrap, results zeroed, shot counts cleared,
+//                 carried events in)                    -> kDonePre
+//   [T+1, 2T+1)   shot assignment of each tile, staged  -> kDoneAsg
+//   2T+1          prefix of the tiles' kept counts      -> kDoneTsc
+//   [2T+2, 3T+2)  placement of each tile's kept events  -> kDonePlc
+//   3T+2          statistics, shot offsets, close rule, segment table
+//                                                       -> kDoneGrp
+//   [3T+3, +S)    one segment each (fused components, moments, hits)
+//                                                       -> kDoneCl
+//   3T+3+S        prefix of the segments' hit counts, carry of open shots
+//                                                       -> kDoneFin
+//   then          hit compaction, eight segments per item.
+// The last workgroup to leave resets the counters for the next launch.
+constexpr int kChunkThreads = 512;
+enum : int { kQTicket = 0, kQExit, kDoneSum, kDonePre, kDoneAsg, kDoneTsc, kDonePlc, kDoneGrp,
+             kDoneCl, kDoneFin, kQWords };
+using ChunkCfg = FusedCfg<4, kChunkThreads, 2048>;
+
+union ChunkLds {
+    AssignLds<kChunkThreads> as;
+    struct {
+        __attribute__((aligned(16))) uint8_t lds[ChunkCfg::kBytes];
+        uint32_t scan_tmp[ChunkCfg::kNW + 1];
+        uint32_t goff[kChunkThreads + 1];
+    } cl;
+    struct {
+        RunSum wbuf[kChunkThreads / 64];
+        TileAcc abuf[kChunkThreads / 64];
+        uint32_t tmp[kChunkThreads / 64 + 1];
+        unsigned long long st[kChunkThreads / 64][8];
+        uint64_t bc[2];
+    } w;
+};
+
+// exclusive in-order fold of one TileAcc per thread of the workgroup
+__device__ inline TileAcc chunk_acc_exscan(TileAcc v, TileAcc* wbuf, uint64_t jump, TileAcc* all) {
+    constexpr int NW = kChunkThreads / 64;
+    const TileAcc inc = wave_acc_inscan(v, jump);
+    TileAcc ex = shfl_up_acc(inc, 1);
+    if (__lane_id() == 0) ex = acc_empty();
+    const int w = threadIdx.x >> 6;
+    if (__lane_id() == 63) wbuf[w] = inc;
+    __syncthreads();
+    TileAcc pre = acc_empty(), tot = acc_empty();
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+        const TileAcc c = wbuf[k];
+        if (k < w) pre = acc_combine(pre, c, jump);
+        tot = acc_combine(tot, c, jump);
+    }
+    __syncthreads();
+    *all = tot;
+    return acc_combine(pre, ex, jump);
+}
+
+// out[0..n] = exclusive prefix of in[0..n), out[n] = total, by one workgroup
+__device__ inline void chunk_scan_u32(const uint32_t* in, uint32_t* out, uint64_t n,
+                                      uint32_t* tmp) {
+    uint32_t run = 0;
+    for (uint64_t base = 0; base < n; base += kChunkThreads) {
+        const uint64_t i = base + threadIdx.x;
+        const uint32_t v = i < n ? in[i] : 0u;
+        uint32_t tot;
+        const uint32_t p = wg_count_scan<kChunkThreads>(v, tmp, &tot);
+        if (i < n) out[i] = run + p;
+        run += tot;
+    }
+    if (threadIdx.x == 0) out[n] = run;
+}
+
+// thread 0 waits until counter q reaches `target`; false after the bound.
+// Relaxed polls with a growing pause (many workgroups may wait on one
+// counter), then one acquire.
+__device__ inline bool chunk_wait(unsigned int* q, unsigned int target) {
+    __shared__ int ok;
+    if (threadIdx.x == 0) {
+        int good = 1;
+        for (uint32_t spin = 0;
+             __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target; ++spin) {
+            if (spin >= (1u << 22)) {
+                good = 0;
+                break;
+            }
+            if (spin < 16) __builtin_amdgcn_s_sleep(1);
+            else if (spin < 256) __builtin_amdgcn_s_sleep(4);
+            else __builtin_amdgcn_s_sleep(16);
+        }
+        (void)__hip_atomic_load(q, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        ok = good;
+    }
+    __syncthreads();
+    const bool r = ok != 0;
+    __syncthreads();  // every thread has read `ok` before the next wait writes it
+    __threadfence();
+    return r;
+}
+
+__device__ inline void chunk_signal(unsigned int* q) {
+    __syncthreads();  // every thread's writes of the item are done
+    if (threadIdx.x == 0) {
+        __threadfence();
+        __hip_atomic_fetch_add(q, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// The arguments come through a pointer to device memory: passed by value,
+// this large a block would be copied to scratch memory in this kernel.  At
+// most four waves per SIMD (the items' code needs up to 128 VGPRs).
+__global__ __launch_bounds__(kChunkThreads) __attribute__((amdgpu_waves_per_eu(4)))
+void k_stream_chunk(const ChunkArgs* __restrict__ pp) {
+    const ChunkArgs& p = *pp;
+    __shared__ ChunkLds L;
+    __shared__ uint32_t s_ticket;
+    const uint32_t tid = threadIdx.x;
+    unsigned int* q = p.qs;
+    DevResults* res = p.a.res;
+    const uint32_t T = p.ntiles, S = p.seg_grid, C = (S + 7) / 8;
+    const uint32_t total = 3 * T + 4 + S + C;
+    for (;;) {
+        if (tid == 0) s_ticket = __hip_atomic_fetch_add(q + kQTicket, 1u, __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        const uint32_t t = s_ticket;
+        __syncthreads();
+        if (t >= total) break;
+        if (t < T) {
+            tile_summary_body(p.a.pk, p.a.n, p.a.sub, p.a.jump, p.sums, p.tdc_slot, t, L.w.wbuf,
+                              L.w.tmp);
+            chunk_signal(q + kDoneSum);
+        } else if (t == T) {
+            const bool ok = chunk_wait(q + kDoneSum, T);
+            // results of the call start at zero (no earlier item writes them)
+            for (uint32_t i = tid; i < sizeof(DevResults) / 8; i += kChunkThreads)
+                ((unsigned long long*)res)[i] = 0;
+            __syncthreads();
+            if (!ok && tid == 0) atomicOr(&res->err, (unsigned long long)kErrSpin);
+            TileAcc v = tid < T ? p.sums[tid] : acc_empty();
+            if (tid == 0) v = acc_combine(p.init, v, p.a.jump);
+            TileAcc all;
+            TileAcc ex = chunk_acc_exscan(v, L.w.abuf, p.a.jump, &all);
+            if (tid == 0) ex = p.init;
+            if (tid == 0) {
+                res->pix_epoch_end = p.pe0 + all.pix.sum;
+                res->tdc_epoch_end = p.te0 + all.tdc.sum;
+                res->pix_last_end = all.pix.last;
+                res->tdc_last_end = all.tdc.last;
+                res->pix_has_end = all.pix.count > 0;
+                res->tdc_has_end = all.tdc.count > 0;
+                res->n_trig = all.ntrig - p.init.ntrig;
+            }
+            if (tid < T)
+                unwrap_tile(ex, p.init.ntrig, tid, p.sums, p.tdc_slot, p.pe0, p.te0, p.a.jump,
+                            p.entries, p.tab_new, res);
+            // shot counts of the window and this call's triggers start at zero,
+            // then the carried events count in
+            const uint64_t rows = p.a.n_win + (all.ntrig - p.init.ntrig) + 2;
+            for (uint64_t i = tid; i < rows; i += kChunkThreads) p.a.shot_cnt[i] = 0;
+            __syncthreads();
+            carry_in_range(p.c_ev_in, p.c_shot_in, p.n_carry, p.carry_rebase, p.ev, nullptr,
+                           p.a.shot_cnt, tid, kChunkThreads);
+            chunk_signal(q + kDonePre);
+        } else if (t < 2 * T + 1) {
+            if (!chunk_wait(q + kDonePre, 1) && tid == 0)
+                atomicOr(&res->err, (unsigned long long)kErrSpin);
+            assign_body<false, true, kChunkThreads>(p.a, t - (T + 1), L.as);
+            chunk_signal(q + kDoneAsg);
+        } else if (t == 2 * T + 1) {
+            // (the prefix too: with no tiles there is no assignment to wait for)
+            if (!(chunk_wait(q + kDonePre, 1) & chunk_wait(q + kDoneAsg, T)) && tid == 0)
+                atomicOr(&res->err, (unsigned long long)kErrSpin);
+            chunk_scan_u32(p.a.tile_cnt, p.tile_off, T, L.w.tmp);
+            chunk_signal(q + kDoneTsc);
+        } else if (t < 3 * T + 2) {
+            if (!chunk_wait(q + kDoneTsc, 1) && tid == 0)
+                atomicOr(&res->err, (unsigned long long)kErrSpin);
+            place_tile(p.a, p.tile_off, p.ev, p.n_carry, p.ev_cap, nullptr, T, t - (2 * T + 2),
+                       kChunkThreads);
+            chunk_signal(q + kDonePlc);
+        } else if (t == 3 * T + 2) {
+            if (!(chunk_wait(q + kDoneTsc, 1) & chunk_wait(q + kDonePlc, T)) && tid == 0)
+                atomicOr(&res->err, (unsigned long long)kErrSpin);
+            // statistics of the tiles
+            unsigned long long v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            if (tid < T) {
+#pragma unroll
+                for (int k = 0; k < 8; ++k) v[k] = p.a.tile_stat[8ull * tid + k];
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                for (int d = 32; d > 0; d >>= 1) {
+                    const unsigned long long o = __shfl_xor(v[k], d, 64);
+                    v[k] = k < 7 ? v[k] + o : max(v[k], o);
+                }
+            if (__lane_id() == 0)
+                for (int k = 0; k < 8; ++k) L.w.st[tid >> 6][k] = v[k];
+            __syncthreads();
+            if (tid == 0) {
+                unsigned long long x[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+                for (int w = 0; w < kChunkThreads / 64; ++w)
+                    for (int k = 0; k < 8; ++k)
+                        x[k] = k < 7 ? x[k] + L.w.st[w][k] : max(x[k], L.w.st[w][k]);
+                res->n_pixels += x[0];
+                res->n_other += x[1];
+                res->n_pre_trigger += x[2];
+                res->n_tof_cut += x[3];
+                res->n_late_drop += x[4];
+                res->n_pix_wraps += x[5];
+                res->n_pix_backjumps += x[6];
+                res->max_t_plus1 = max(res->max_t_plus1, x[7]);
+                res->n_groups = p.a.n_win + res->n_trig;
+                L.w.bc[0] = res->n_groups;
+            }
+            __syncthreads();
+            const uint64_t G = L.w.bc[0];
+            uint32_t* shot_off = const_cast<uint32_t*>(p.c.grp_off);
+            chunk_scan_u32(p.a.shot_cnt, shot_off, G, L.w.tmp);
+            __syncthreads();
+            if (tid == 0)
+                close_rule(p.a.tab, &res->n_trig, p.a.n_win, p.a.first_open, p.flush,
+                           p.max_t_plus1_prev, p.a.tof_max, p.slack, p.c.grp_off, res);
+            __syncthreads();
+            seg_table_range(p.c.grp_off, p.c.n_grp_dev, p.c.n_ev_dev, p.c.skip, p.c.q,
+                            const_cast<uint32_t*>(p.c.seg_lo), res, tid, kChunkThreads);
+            chunk_signal(q + kDoneGrp);
+        } else if (t < 3 * T + 3 + S) {
+            if (!chunk_wait(q + kDoneGrp, 1) && tid == 0)
+                atomicOr(&res->err, (unsigned long long)kErrSpin);
+            fused_segment<4, kChunkThreads, 2048>(p.c, t - (3 * T + 3), false, L.cl.lds,
+                                                  L.cl.scan_tmp, L.cl.goff);
+            chunk_signal(q + kDoneCl);
+        } else if (t == 3 * T + 3 + S) {
+            if (!(chunk_wait(q + kDoneGrp, 1) & chunk_wait(q + kDoneCl, S)) && tid == 0)
+                atomicOr(&res->err, (unsigned long long)kErrSpin);
+            chunk_scan_u32(p.c.seg_cnt, const_cast<uint32_t*>(p.c.seg_off), res->n_seg, L.w.tmp);
+            carry_out_range(p.ev, nullptr, nullptr, p.c.grp_off, &res->n_groups, &res->n_close_ev,
+                            &res->n_kept, p.c_gidx_in, p.n_carry, p.c.ev_base, p.c_ev_out,
+                            p.c_shot_out, p.c_gidx_out, p.carry_cap, res, tid, kChunkThreads);
+            chunk_signal(q + kDoneFin);
+        } else {
+            if (!chunk_wait(q + kDoneFin, 1) && tid == 0)
+                atomicOr(&res->err, (unsigned long long)kErrSpin);
+            hit_compact_wave(p.c, (uint64_t)(t - (3 * T + 4 + S)) * 8 + (tid >> 6));
+        }
+        __syncthreads();  // LDS and the ticket are reused by the next item
+    }
+    if (tid == 0) {
+        const unsigned int e = __hip_atomic_fetch_add(q + kQExit, 1u, __ATOMIC_ACQ_REL,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+        if (e == gridDim.x - 1)  // every other workgroup has left: reset for the next launch
+            for (int i = 0; i < kQWords; ++i)
+                __hip_atomic_store(q + i, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+uint32_t chunk_max_tiles() { return kChunkThreads; }
+uint32_t chunk_queue_words() { return kQWords; }
+
+void launch_stream_chunk(const ChunkArgs& p, const ChunkArgs* p_dev, uint32_t grid, hipStream_t s) {
+    const uint64_t total = 3ull * p.ntiles + 4 + p.seg_grid + (p.seg_grid + 7) / 8;
+    const uint64_t want = grid ? grid : 1;
+    const uint32_t g = (uint32_t)(total < want ? total : want);
+    hipLaunchKernelGGL(k_stream_chunk, dim3(g), dim3(kChunkThreads), 0, s, p_dev);
 }
 
 }  // namespace tpx

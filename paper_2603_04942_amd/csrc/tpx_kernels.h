@@ -113,6 +113,43 @@ void launch_seg_centroid(const ClusterArgs& a, uint64_t grid, hipStream_t s);
 void launch_cluster_fused(const ClusterArgs& a, uint64_t grid, int variant, uint32_t* defer_list,
                           uint32_t list_grid, hipStream_t s);
 void launch_hit_compact(const ClusterArgs& a, uint64_t grid, hipStream_t s);
+
+// The fast stream path of one chunk in one persistent launch (tpx_cluster.hip,
+// k_stream_chunk): `a` and `c` as for the separate launches (a staged, with
+// the staging buffers; c with the group table, segment table and the counts
+// of the call's results), plus what the prefix, close rule and carry need.
+// qs: kQWords counters, zero before the first launch (each launch leaves them
+// zero).  At most chunk_max_tiles() tiles.
+struct ChunkArgs {
+    AssignArgs a;
+    ClusterArgs c;
+    TileAcc* sums;
+    uint64_t* tdc_slot;
+    TileEntry* entries;
+    uint64_t* tab_new;                 // this call's triggers: tab + n_win
+    TileAcc init;                      // counter state in force at the call's start
+    int64_t pe0, te0;
+    uint32_t* tile_off;                // ntiles + 1
+    uint64_t* ev;                      // kept events: carried, then this call's
+    uint64_t ev_cap;
+    const uint64_t* c_ev_in;
+    const uint32_t* c_shot_in;
+    uint64_t n_carry;
+    uint32_t carry_rebase;
+    int flush;
+    uint64_t max_t_plus1_prev, slack;
+    const uint64_t* c_gidx_in;
+    uint64_t* c_ev_out;
+    uint32_t* c_shot_out;
+    uint64_t* c_gidx_out;
+    uint64_t carry_cap;
+    unsigned int* qs;
+    uint32_t ntiles, seg_grid;
+};
+// p_dev: a device copy of p, complete when the launch runs (stream order)
+void launch_stream_chunk(const ChunkArgs& p, const ChunkArgs* p_dev, uint32_t grid, hipStream_t s);
+uint32_t chunk_max_tiles();
+uint32_t chunk_queue_words();
 int fused_variants();
 const char* fused_variant_name(int variant);
 // patches of the hits written by the stream call whose cluster arguments are

@@ -1,7 +1,7 @@
 // Small device utilities of libtpx: fills, prefix sums, the close rule,
 // the stable split sort used when events are not in shot order, carry
 // copies between stream chunks, and centroids of externally given labels.
-#include "tpx_kernels.h"
+#include "tpx_util_dev.h"
 
 namespace tpx {
 
@@ -127,35 +127,13 @@ void launch_scan_u32(const uint32_t* in, uint32_t* out, uint64_t n_host,
                        n_dev, block_tmp);
 }
 
-// Shots [first_open, s_close) close in this chunk: trigger s+1 was seen and a
-// word later than T[s] + tof_max + slack has arrived (everything on flush).
+// the close rule of close_rule (tpx_util_dev.h)
 __global__ void k_close(const uint64_t* tab, const unsigned long long* n_trig_dev, uint64_t n_win,
                         uint64_t first_open, int flush, uint64_t max_t_plus1_prev,
                         uint64_t tof_max, uint64_t slack, const uint32_t* shot_off,
                         DevResults* res) {
-    const uint64_t n_tab = n_win + *n_trig_dev;
-    uint64_t s_close;
-    if (flush) {
-        s_close = n_tab;
-    } else {
-        uint64_t mt1 = max<uint64_t>(max_t_plus1_prev, res->max_t_plus1);
-        if (n_tab) mt1 = max<uint64_t>(mt1, tab[n_tab - 1] + 1);
-        uint64_t ub = 0;
-        if (mt1 > tof_max + slack + 0) {
-            const uint64_t lim = mt1 - 1 - tof_max - slack;  // T[s] <= lim closes s
-            uint64_t lo = 0, hi = n_tab;
-            while (lo < hi) {
-                const uint64_t m = (lo + hi) >> 1;
-                if (tab[m] <= lim) lo = m + 1; else hi = m;
-            }
-            ub = lo;
-        }
-        s_close = n_tab ? min<uint64_t>(ub, n_tab - 1) : 0;
-        s_close = max<uint64_t>(s_close, min<uint64_t>(first_open, n_tab));
-    }
-    res->n_groups = n_tab;
-    res->n_close_grp = s_close;
-    res->n_close_ev = shot_off ? shot_off[s_close] : 0;
+    close_rule(tab, n_trig_dev, n_win, first_open, flush, max_t_plus1_prev, tof_max, slack,
+               shot_off, res);
 }
 void launch_close(const uint64_t* tab, const unsigned long long* n_trig_dev, uint64_t n_win,
                   uint64_t first_open, int flush, uint64_t max_t_plus1_prev, uint64_t tof_max,
@@ -307,13 +285,9 @@ void launch_gather_packed(const uint64_t* ev, const uint32_t* perm, uint64_t* ou
 // ------------------------------------------------------------ stream carry
 __global__ void k_carry_in(const uint64_t* c_ev, const uint32_t* c_shot, uint64_t n_carry,
                            uint32_t rebase, uint64_t* ev, uint32_t* shot_arr, uint32_t* shot_cnt) {
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_carry;
-         i += (uint64_t)gridDim.x * blockDim.x) {
-        ev[i] = c_ev[i];
-        const uint32_t sidx = c_shot[i] - rebase;
-        if (shot_arr) shot_arr[i] = sidx;
-        if (shot_cnt) atomicAdd(&shot_cnt[sidx], 1u);
-    }
+    carry_in_range(c_ev, c_shot, n_carry, rebase, ev, shot_arr, shot_cnt,
+                   (uint64_t)blockIdx.x * blockDim.x + threadIdx.x,
+                   (uint64_t)gridDim.x * blockDim.x);
 }
 void launch_carry_in(const uint64_t* c_ev, const uint32_t* c_shot, uint64_t n_carry,
                      uint32_t rebase, uint64_t* ev, uint32_t* shot_arr, uint32_t* shot_cnt,
@@ -329,33 +303,10 @@ __global__ void k_carry_out(const uint64_t* ev, const uint32_t* perm, const uint
                             const uint64_t* carry_gidx_in, uint64_t n_carry, uint64_t ev_base,
                             uint64_t* c_ev, uint32_t* c_shot, uint64_t* c_gidx, uint64_t carry_cap,
                             DevResults* res) {
-    const uint64_t lo = *n_close_ev;
-    const uint64_t hi = n_carry + *n_kept;
-    if (hi > lo && hi - lo > carry_cap) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&res->err, (unsigned long long)kErrCapacity);
-        return;
-    }
-    const uint64_t rows = n_rows_dev ? *n_rows_dev : 0;
-    for (uint64_t p = lo + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < hi;
-         p += (uint64_t)gridDim.x * blockDim.x) {
-        const uint64_t j = p - lo;
-        c_ev[j] = ev[p];
-        uint32_t sidx;
-        if (shot_arr) {
-            sidx = shot_arr[p];
-        } else {  // last row g with shot_off[g] <= p
-            uint64_t a = 0, b = rows;
-            while (b - a > 1) {
-                const uint64_t m = (a + b) >> 1;
-                if (shot_off[m] <= p) a = m; else b = m;
-            }
-            sidx = (uint32_t)a;
-        }
-        c_shot[j] = sidx;
-        if (p == hi - 1) res->carry_last = (unsigned long long)sidx + 1;
-        const uint64_t o = perm ? perm[p] : p;
-        c_gidx[j] = o < n_carry ? carry_gidx_in[o] : ev_base + (o - n_carry);
-    }
+    carry_out_range(ev, perm, shot_arr, shot_off, n_rows_dev, n_close_ev, n_kept, carry_gidx_in,
+                    n_carry, ev_base, c_ev, c_shot, c_gidx, carry_cap, res,
+                    (uint64_t)blockIdx.x * blockDim.x + threadIdx.x,
+                    (uint64_t)gridDim.x * blockDim.x);
 }
 void launch_carry_out(const uint64_t* ev, const uint32_t* perm, const uint32_t* shot_arr,
                       const uint32_t* shot_off, const unsigned long long* n_rows_dev,

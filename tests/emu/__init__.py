@@ -61,16 +61,23 @@ def run_cluster(ev, dxy=1, dt_ticks=128, preempt=0, seed=1, timeout=600):
     return st, nc, lab, _errors(out, 12 + 4 * n)
 
 
-def run_stream(packets, chunk, pix_epoch0=0, tdc_epoch0=0, q=0, kernel=0, preempt=0, seed=1,
-               timeout=600):
-    """tpx_process_stream over the packets in chunks (flush on the last),
-    with the given clustering kernel (-1 staged, >= 0 a fused variant);
-    returns (status, hits, emulator findings)."""
+def run_stream(packets, chunk, pix_epoch0=0, tdc_epoch0=0, q=0, kernel=0, persistent=1,
+               preempt=0, seed=1, timeout=600):
+    """tpx_process_stream over the packets in chunks of `chunk` words, or of
+    the sizes in a list (flush on the last),
+    with the given clustering kernel (-1 staged, >= 0 a fused variant) and
+    the persistent launch of small chunks on or off; returns (status, hits,
+    emulator findings)."""
     pk = np.ascontiguousarray(packets, dtype=np.uint64)
+    sizes = b""
+    if not np.isscalar(chunk):  # a list of chunk sizes
+        sizes = np.array([len(chunk)] + list(chunk), np.uint64).tobytes()
+        chunk = 0
     blob = b"".join([np.array([pk.size, chunk], np.uint64).tobytes(),
                      np.array([pix_epoch0, tdc_epoch0], np.int64).tobytes(),
-                     np.array([q], np.uint32).tobytes(), np.array([kernel], np.int32).tobytes(),
-                     pk.tobytes()])
+                     np.array([q], np.uint32).tobytes(),
+                     np.array([kernel, persistent], np.int32).tobytes(),
+                     sizes, pk.tobytes()])
     out, _ = _run("stream", blob, preempt, seed, timeout)
     st = int(np.frombuffer(out, np.int32, 1, 0)[0])
     nh = int(np.frombuffer(out, np.uint64, 1, 4)[0])

@@ -24,7 +24,8 @@ FLAGS = ["-std=c++17", "-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=addre
 
 def _inputs():
     files = [os.path.join(CSRC, s) for s in HIP_SOURCES]
-    files += [os.path.join(CSRC, h) for h in ("tpx_internal.h", "tpx_kernels.h")]
+    files += [os.path.join(CSRC, h) for h in ("tpx_internal.h", "tpx_kernels.h",
+                                              "tpx_decode_dev.h", "tpx_util_dev.h")]
     files += [os.path.join(ROOT, "include", "tpx.h")]
     files += [os.path.join(HERE, f) for f in ("hip_emu.h", "hip_emu.cpp", "emu_main.cpp",
                                                "emu_selftest.cpp", "build.py")]

@@ -8,7 +8,8 @@
 //   emu_tpx stream IN OUT    IN: u64 n, u64 chunk, i64 pix_epoch0,
 //                                i64 tdc_epoch0, u32 q, i32 kernel
 //                                (-1 staged, >= 0 fused variant),
-//                                packets u64[n]
+//                                i32 persistent (0 / 1), [chunk 0: u64 count,
+//                                u64 sizes[count]], packets u64[n]
 //                            OUT: i32 status, u64 n_hits, tpx_hit[n_hits]
 // Both append: u64 error-text length, error text (empty = no finding).
 //   emu_tpx selftest         runs kernels with planted synchronisation
@@ -111,22 +112,34 @@ int run_stream(In& in, FILE* out) {
     const int64_t pe0 = in.get<int64_t>(), te0 = in.get<int64_t>();
     const uint32_t q = in.get<uint32_t>();
     const int32_t kern = in.get<int32_t>();
+    const int32_t persist = in.get<int32_t>();
+    // chunk 0: a list of chunk sizes follows (u64 count, u64 sizes)
+    std::vector<uint64_t> sizes;
+    if (chunk == 0) {
+        sizes.resize(in.get<uint64_t>());
+        for (auto& z : sizes) z = in.get<uint64_t>();
+    }
     uint64_t* pk = dev<uint64_t>(n);
     in.arr(pk, n);
+    uint64_t max_chunk = chunk;
+    for (uint64_t z : sizes) max_chunk = std::max(max_chunk, z);
     tpx_params p;
     tpx_params_default(&p);
     p.pix_epoch0 = pe0;
     p.tdc_epoch0 = te0;
     tpx_stream* s = nullptr;
-    int32_t st = tpx_stream_create(&p, chunk, &s);
+    int32_t st = tpx_stream_create(&p, max_chunk ? max_chunk : 1, &s);
     std::vector<tpx_hit> all;
     if (st == TPX_OK && q) st = tpx_stream_set_segment(s, q);
     if (st == TPX_OK) st = tpx_stream_set_kernel(s, kern);
+    if (st == TPX_OK) st = tpx_stream_set_persistent(s, persist ? 512 : 0);
     const size_t cap = n + 16;
     tpx_hit* hits = dev<tpx_hit>(cap);
-    for (uint64_t off = 0; st == TPX_OK;) {
-        const uint64_t m = std::min<uint64_t>(chunk, n - off);
-        const int flush = off + m >= n;
+    for (uint64_t off = 0, k = 0; st == TPX_OK; ++k) {
+        const uint64_t want = chunk ? chunk : (k < sizes.size() ? sizes[k] : n - off);
+        const uint64_t m = std::min<uint64_t>(want, n - off);
+        // with a size list, the last entry flushes (it may be empty)
+        const int flush = chunk ? off + m >= n : k + 1 >= sizes.size();
         size_t nh = 0;
         st = tpx_process_stream(s, pk + off, m, flush, hits, cap, &nh, nullptr, nullptr);
         if (st != TPX_OK) {

@@ -104,4 +104,6 @@ def test_learned_and_tuning_argument_errors_need_no_gpu():
     assert lib.tpx_stream_kernel_name(-1) and lib.tpx_stream_kernel_name(0)
     assert lib.tpx_stream_set_kernel(None, 0) == tpx.EINVAL
     assert lib.tpx_stream_get_kernel(None) == -2
+    assert lib.tpx_stream_set_persistent(None, 4) == tpx.EINVAL
+    assert lib.tpx_stream_get_persistent(None) == -1
     assert lib.tpx_stream_set_patches(None, 1) == tpx.EINVAL

@@ -101,8 +101,31 @@ def test_stream_kernels(emu, orc, kernel, name, shots, chunk):
     kw = dict(pix_epoch0=w.pix_epoch0, tdc_epoch0=w.tdc_epoch0)
     ref, _ = orc.run(w.packets, **kw)
     for ch in (1 << 22, chunk):
-        st, hits, errs = emu.run_stream(w.packets, ch, kernel=kernel, preempt=100,
+        st, hits, errs = emu.run_stream(w.packets, ch, kernel=kernel, persistent=0, preempt=100,
                                         seed=11 + kernel, **kw)
+        assert errs == ""
+        assert st == 0
+        _assert_hits(hits, ref)
+
+
+@pytest.mark.parametrize("persistent", [0, 1])
+@pytest.mark.parametrize("name,shots,chunks", [("c1", 60, (1500, 40000)), ("c5", 8, (8192, 3000)),
+                                               ("c3", 12, (30000, 1 << 22))])
+def test_stream_persistent_launch(emu, orc, persistent, name, shots, chunks):
+    """The fast path of small chunks in one persistent launch (work items by
+    ticket in dependency order: tile summaries, the prefix over tiles,
+    assignment, placement, grouping, segments, carry, compaction) against the
+    separate launches' results and the oracle, in chunks that split shots,
+    with and without it."""
+    w = synth.make_config(name, n_shots=shots)
+    kw = dict(pix_epoch0=w.pix_epoch0, tdc_epoch0=w.tdc_epoch0)
+    ref, _ = orc.run(w.packets, **kw)
+    # fixed sizes, then uneven sizes that end with an empty flushing chunk
+    rng = np.random.default_rng(7)
+    uneven = list(rng.integers(500, 20000, w.n_packets // 5000 + 2)) + [w.n_packets, 0]
+    for ch in list(chunks) + [uneven]:
+        st, hits, errs = emu.run_stream(w.packets, ch, kernel=1, persistent=persistent,
+                                        preempt=100, seed=3 + persistent, **kw)
         assert errs == ""
         assert st == 0
         _assert_hits(hits, ref)
@@ -124,7 +147,7 @@ def test_stream_fused_capacity_paths(emu, orc, kernel, case):
           "iso9000": lambda: many_components_packets(9000),
           "square": lambda: big_component_packets(side=60, layers=2)}[case]()
     ref, _ = orc.run(pk)
-    st, hits, errs = emu.run_stream(pk, 1 << 22, kernel=kernel, preempt=100, seed=5)
+    st, hits, errs = emu.run_stream(pk, 1 << 22, kernel=kernel, persistent=0, preempt=100, seed=5)
     assert errs == ""
     assert st == 0
     _assert_hits(hits, ref)

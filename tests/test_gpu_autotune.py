@@ -34,13 +34,15 @@ def c3(orc):
 @pytest.mark.parametrize("q", [64, 100, 333, 512, 2048, 4096])
 def test_stride_parity_uneven_shots(tpx, c3, q):
     w, ref, rst = c3
-    for k in range(-1, tpx.kernel_count()):
+    # every kernel in separate launches, then the persistent launch (None)
+    for k in list(range(-1, tpx.kernel_count())) + [None]:
         print(f"c3 300 shots, stride {q}, kernel {k}", flush=True)
         sys.stdout.flush()
-        s = tpx.Stream(w.n_packets, pix_epoch0=w.pix_epoch0, tdc_epoch0=w.tdc_epoch0, kernel=k)
+        s = tpx.Stream(w.n_packets, pix_epoch0=w.pix_epoch0, tdc_epoch0=w.tdc_epoch0,
+                       kernel=1 if k is None else k, persistent=k is None)
         try:
             s.set_segment(q)
-            assert s.segment() == q and s.kernel() == k
+            assert s.segment() == q and s.kernel() == (1 if k is None else k)
             h, st = s.process(w.packets, flush=True)
         finally:
             s.close()

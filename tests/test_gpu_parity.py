@@ -101,21 +101,26 @@ def test_decode_across_wraps_and_calls(tpx, orc):
 
 
 # ------------------------------------------------------------------ stream
+@pytest.mark.parametrize("persistent", [True, False])
 @pytest.mark.parametrize("name,shots", [("c1", 1000), ("c2", 300), ("c3", 120), ("c5", 150)])
-def test_stream_whole(tpx, orc, name, shots):
-    _say(f"stream whole {name} shots={shots}")
+def test_stream_whole(tpx, orc, name, shots, persistent):
+    """Whole streams as one chunk, in one persistent launch (these chunks
+    are small enough) and in separate launches."""
+    _say(f"stream whole {name} shots={shots} persistent={persistent}")
     w = synth.make_config(name, n_shots=shots)
     kw = dict(pix_epoch0=w.pix_epoch0, tdc_epoch0=w.tdc_epoch0)
     ref, rst = orc.run(w.packets, **kw)
-    h, st = tpx.process_stream(w.packets, **kw)
+    h, st = tpx.process_stream(w.packets, persistent=persistent, **kw)
     assert_hits_match(h, ref)
     for f in ("n_pixels", "n_tdc", "n_other", "n_pre_trigger", "n_tof_cut", "n_events"):
         assert st[f] == rst[f], f
     assert st["n_hits"] == ref.size and st["n_late_drop"] == 0
 
 
-@pytest.mark.parametrize("seed", range(4))
+@pytest.mark.parametrize("seed", range(6))
 def test_stream_chunked(tpx, orc, seed):
+    """Random splits of a stream (odd seeds in separate launches, even ones
+    in persistent launches); chunks may be empty of triggers or pixels."""
     w = synth.make_config("c5", n_shots=120)
     kw = dict(pix_epoch0=w.pix_epoch0, tdc_epoch0=w.tdc_epoch0)
     ref, _ = orc.run(w.packets, **kw)
@@ -123,7 +128,7 @@ def test_stream_chunked(tpx, orc, seed):
     k = int(rng.integers(2, 40))
     cuts = np.sort(rng.choice(np.arange(1, w.n_packets), k, replace=False))
     parts = np.split(w.packets, cuts)
-    s = tpx.Stream(max(len(p) for p in parts), **kw)
+    s = tpx.Stream(max(len(p) for p in parts), persistent=seed % 2 == 0, **kw)
     out = []
     for i, part in enumerate(parts):
         h, st = s.process(part, flush=(i == len(parts) - 1))
@@ -132,6 +137,25 @@ def test_stream_chunked(tpx, orc, seed):
     h = np.concatenate(out)
     assert_hits_match(h, ref)
     assert s.fallback_count == 0
+
+
+@pytest.mark.parametrize("persistent", [True, False])
+def test_stream_ends_with_empty_flush(tpx, orc, persistent):
+    """A stream whose last call flushes no new words: the open shots carried
+    so far are closed by a call with no tiles (in the persistent launch every
+    item then waits for the prefix over tiles directly)."""
+    w = synth.make_config("c1", n_shots=500)
+    kw = dict(pix_epoch0=w.pix_epoch0, tdc_epoch0=w.tdc_epoch0)
+    ref, _ = orc.run(w.packets, **kw)
+    s = tpx.Stream(5000, persistent=persistent, **kw)
+    out = []
+    for a in range(0, w.n_packets, 5000):
+        h, _ = s.process(w.packets[a:a + 5000], flush=False)
+        out.append(h)
+    h, st = s.process(w.packets[:0], flush=True)
+    out.append(h)
+    assert h.size > 0 and st["n_events"] == 0
+    assert_hits_match(np.concatenate(out), ref)
 
 
 @pytest.mark.parametrize("n_iso", [1500, 3000, 20000])
@@ -145,8 +169,10 @@ def test_stream_many_components(tpx, orc, n_iso):
     ref, _ = orc.run(pk)
     assert ref.size > 1024
     for k in range(-1, tpx.kernel_count()):
-        h, _ = tpx.process_stream(pk, kernel=k)
+        h, _ = tpx.process_stream(pk, kernel=k, persistent=False)
         assert_hits_match(h, ref)
+    h, _ = tpx.process_stream(pk, persistent=True)
+    assert_hits_match(h, ref)
 
 
 def test_stream_component_beyond_32bit_moments(tpx, orc):
@@ -158,8 +184,10 @@ def test_stream_component_beyond_32bit_moments(tpx, orc):
     ref, _ = orc.run(pk)
     assert ref.size == 1 and ref["npix"][0] == 36992
     for k in range(-1, tpx.kernel_count()):
-        h, _ = tpx.process_stream(pk, kernel=k)
+        h, _ = tpx.process_stream(pk, kernel=k, persistent=False)
         assert_hits_match(h, ref)
+    h, _ = tpx.process_stream(pk, persistent=True)
+    assert_hits_match(h, ref)
 
 
 def test_streams_concurrent_on_two_hip_streams(tpx, orc):
