@@ -54,7 +54,7 @@ def stage_bytes(n_packets, n_events, n_hits, fused):
 
 
 KERNEL_SOURCES = ("tpx_decode.hip", "tpx_cluster.hip", "tpx_util.hip", "tpx_internal.h",
-                  "tpx_kernels.h")
+                  "tpx_kernels.h", "tpx_decode_dev.h", "tpx_util_dev.h")
 
 
 def source_digest():

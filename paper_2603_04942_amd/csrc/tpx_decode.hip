@@ -77,7 +77,7 @@ __global__ void k_trig_unwrap(const TileAcc* __restrict__ sums, const TileAcc* _
 
 template <bool kSoA, bool kStaged = false>
 __global__ __launch_bounds__(kTileThreads) void k_assign(AssignArgs a) {
-    __shared__ AssignLds<kTileThreads> L;
+    __shared__ AssignLds<kTileThreads, kSoA> L;
     assign_body<kSoA, kStaged, kTileThreads>(a, blockIdx.x, L);
 }
 

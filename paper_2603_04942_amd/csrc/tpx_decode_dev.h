@@ -227,12 +227,18 @@ __device__ inline uint64_t upper_bound_u64(P a, uint64_t lo, uint64_t hi, uint64
 // kStaged (packed output only): tile = workgroup index, no look-back; the
 // kept events go to the tile's own staging range and the tile's counts,
 // shot range and statistics to per-tile records.
+// Packed output (the stream path) reads each thread's words straight into
+// registers and writes its kept events from there; the SoA output stages the
+// tile through LDS.
+constexpr bool kAssignDirect = true;
+
 // LDS of one assignment workgroup of kThreads threads
-template <int kThreads>
+template <int kThreads, bool kSoA = false>
 struct AssignLds {
     static constexpr int kItems = kTilePkts / kThreads;  // consecutive words per thread
     static constexpr int kW = kThreads / 64;
-    uint64_t sp[kTileLds];
+    static constexpr bool kDirect = kAssignDirect && !kSoA;
+    uint64_t sp[kDirect ? 2 : kTileLds];
     uint64_t slice[kTrigSlice + 1];
     RunSum wbuf[kW];
     uint32_t w_cnt[kW], w_max[kW], w_min[kW];
@@ -242,8 +248,10 @@ struct AssignLds {
 
 template <bool kSoA, bool kStaged, int kThreads>
 __device__ __forceinline__ void assign_body(const AssignArgs& a, uint32_t tile_staged,
-                                            AssignLds<kThreads>& L) {
-    constexpr int kItems = AssignLds<kThreads>::kItems, kW = AssignLds<kThreads>::kW;
+                                            AssignLds<kThreads, kSoA>& L) {
+    using LdsT = AssignLds<kThreads, kSoA>;
+    constexpr int kItems = LdsT::kItems, kW = LdsT::kW;
+    constexpr bool kDirect = LdsT::kDirect;
     uint64_t* sp = L.sp;
     uint64_t* slice = L.slice;
     uint64_t* bcast = L.bcast;
@@ -258,11 +266,16 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, uint32_t tile_s
         tile = __builtin_amdgcn_readfirstlane((uint32_t)bcast[0]);
     }
     const uint64_t base = (uint64_t)tile * kTilePkts;
+    uint64_t rw[kDirect ? kItems : 1];
+    if constexpr (kDirect) {
+        load_run<kItems>(a.pk, base + (uint64_t)threadIdx.x * kItems, a.n, rw);
+    } else {
 #pragma unroll
-    for (int k = 0; k < kItems; ++k) {
-        const int i = k * kThreads + threadIdx.x;
-        const uint64_t g = base + (uint64_t)i;
-        sp[tile_slot(i)] = g < a.n ? __builtin_nontemporal_load(a.pk + g) : 0ull;
+        for (int k = 0; k < kItems; ++k) {
+            const int i = k * kThreads + threadIdx.x;
+            const uint64_t g = base + (uint64_t)i;
+            sp[tile_slot(i)] = g < a.n ? __builtin_nontemporal_load(a.pk + g) : 0ull;
+        }
     }
     const TileEntry e = a.entries[tile];
     const uint64_t n_tab = a.n_win + *a.n_trig_dev;
@@ -289,7 +302,7 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, uint32_t tile_s
         const int i = threadIdx.x * kItems + j;
         tv[j] = kNotPixel;
         if (i < nvalid) {
-            const Word d = decode_word(sp[tile_slot(i)], a.sub);
+            const Word d = decode_word(kDirect ? rw[kDirect ? j : 0] : sp[tile_slot(i)], a.sub);
             if (d.kind == kPixel) {
                 tv[j] = d.raw | ((uint64_t)d.x << 34) | ((uint64_t)d.y << 42) | ((uint64_t)d.tot << 50);
                 P = run_push(P, d.raw, a.jump);
@@ -505,25 +518,40 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, uint32_t tile_s
             }
         }
     } else {
-        // kept events staged in LDS in output order, then written contiguously
-        {
-            uint32_t q = tpre;
+        if constexpr (kDirect) {
+            // kept events (and shots) from registers, each thread's in order
+            uint64_t o = out0 + tpre;
 #pragma unroll
-            for (int j = 0; j < kItems; ++j)
-                if (sv[j] != kNo) sp[tile_slot(q++)] = tv[j];
-        }
-        __syncthreads();
-        for (uint32_t k = threadIdx.x; k < tile_keep; k += kThreads)
-            if (out0 + k < a.ev_cap) a.ev[out0 + k] = sp[tile_slot(k)];
-        if (a.shot_out) {
-            __syncthreads();
-            uint32_t q = tpre;
+            for (int j = 0; j < kItems; ++j) {
+                if (sv[j] != kNo) {
+                    if (o < a.ev_cap) {
+                        a.ev[o] = tv[j];
+                        if (a.shot_out) a.shot_out[o] = sv[j];
+                    }
+                    ++o;
+                }
+            }
+        } else {
+            // kept events staged in LDS in output order, then written contiguously
+            {
+                uint32_t q = tpre;
 #pragma unroll
-            for (int j = 0; j < kItems; ++j)
-                if (sv[j] != kNo) sp[tile_slot(q++)] = sv[j];
+                for (int j = 0; j < kItems; ++j)
+                    if (sv[j] != kNo) sp[tile_slot(q++)] = tv[j];
+            }
             __syncthreads();
             for (uint32_t k = threadIdx.x; k < tile_keep; k += kThreads)
-                if (out0 + k < a.ev_cap) a.shot_out[out0 + k] = (uint32_t)sp[tile_slot(k)];
+                if (out0 + k < a.ev_cap) a.ev[out0 + k] = sp[tile_slot(k)];
+            if (a.shot_out) {
+                __syncthreads();
+                uint32_t q = tpre;
+#pragma unroll
+                for (int j = 0; j < kItems; ++j)
+                    if (sv[j] != kNo) sp[tile_slot(q++)] = sv[j];
+                __syncthreads();
+                for (uint32_t k = threadIdx.x; k < tile_keep; k += kThreads)
+                    if (out0 + k < a.ev_cap) a.shot_out[out0 + k] = (uint32_t)sp[tile_slot(k)];
+            }
         }
         // events per shot from run boundaries: a run of shot s over positions
         // [p, p') adds p' - p to its count.  Exact when the kept events are in

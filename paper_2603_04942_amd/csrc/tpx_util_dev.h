@@ -37,17 +37,42 @@ __device__ __forceinline__ void close_rule(const uint64_t* tab, const unsigned l
     res->n_close_grp = s_close;
     res->n_close_ev = shot_off ? shot_off[s_close] : 0;
 }
-// the carried events i = first, first + stride, ... < n_carry
-__device__ __forceinline__ void carry_in_range(const uint64_t* c_ev, const uint32_t* c_shot, uint64_t n_carry,
-                               uint32_t rebase, uint64_t* ev, uint32_t* shot_arr,
-                               uint32_t* shot_cnt, uint64_t first, uint64_t stride) {
-    for (uint64_t i = first; i < n_carry; i += stride) {
-        ev[i] = c_ev[i];
-        const uint32_t sidx = c_shot[i] - rebase;
-        if (shot_arr) shot_arr[i] = sidx;
-        if (shot_cnt) atomicAdd(&shot_cnt[sidx], 1u);
+// the carried events i = first, first + stride, ... < n_carry.  The carried
+// events are in shot order; when the lanes of a wave hold consecutive events
+// (first = the thread's global index, stride a multiple of 64), each run of
+// one shot within a wave adds its length with one atomic (the run's last
+// lane), else every event adds one.
+__device__ __forceinline__ void carry_in_range(const uint64_t* c_ev, const uint32_t* c_shot,
+                                               uint64_t n_carry, uint32_t rebase, uint64_t* ev,
+                                               uint32_t* shot_arr, uint32_t* shot_cnt,
+                                               uint64_t first, uint64_t stride) {
+    const bool runs = (stride & 63) == 0 && (first & 63) == __lane_id();
+    for (uint64_t base = first - (first & 63); base < n_carry; base += stride) {
+        const uint64_t i = base + (first & 63);
+        const bool live = i < n_carry;
+        uint32_t sidx = 0;
+        if (live) {
+            ev[i] = c_ev[i];
+            sidx = c_shot[i] - rebase;
+            if (shot_arr) shot_arr[i] = sidx;
+        }
+        if (!shot_cnt) continue;
+        if (!runs) {
+            if (live) atomicAdd(&shot_cnt[sidx], 1u);
+            continue;
+        }
+        // lanes of this wave hold events base .. base + 63 (all lanes take
+        // part, so the cross-lane reads are defined)
+        const int lane = (int)__lane_id();
+        const uint32_t next = __shfl_down(sidx, 1, 64);
+        const bool last = live && (lane == 63 || i + 1 >= n_carry || next != sidx);
+        const uint64_t ends = __ballot(last);
+        const uint64_t below = ends & ((1ull << lane) - 1ull);
+        const int start = below ? 64 - __clzll(below) : 0;
+        if (last) atomicAdd(&shot_cnt[sidx], (uint32_t)(lane - start + 1));
     }
 }
+
 // events of the open shots, positions lo + first, lo + first + stride, ...
 __device__ __forceinline__ void carry_out_range(const uint64_t* ev, const uint32_t* perm, const uint32_t* shot_arr,
                                 const uint32_t* shot_off, const unsigned long long* n_rows_dev,
