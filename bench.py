@@ -478,6 +478,54 @@ def run_uneven(args, w):
                 events_per_s=st.n_events / (ms * 1e-3))
 
 
+def run_out_of_order(args, wl):
+    """The c2 step with three kept pixels each reported after a pixel of a
+    later shot: the chunk is no longer in shot order, so the stream takes the
+    general path (every event's shot materialised, a stable 4-bit radix sort
+    by shot, clustering through the permutation).  Timed like the c2 step,
+    host clock over whole calls."""
+    import torch
+
+    import paper_2603_04942_amd as tpx
+
+    pk_h = wl.packets.copy()
+    rng = np.random.default_rng(5)
+    n = pk_h.size
+    pix = np.nonzero((pk_h[n // 10: 9 * n // 10] >> np.uint64(60)) == np.uint64(0xB))[0] + n // 10
+    moves = sorted(((int(a), int(a) + int(d)) for a, d in
+                    zip(rng.choice(pix, 3, replace=False), rng.integers(2000, 5000, 3))),
+                   reverse=True)
+    for i, j in moves:          # word i moved behind word j (later moves first)
+        pk_h = np.concatenate([pk_h[:i], pk_h[i + 1:j + 1], pk_h[i:i + 1], pk_h[j + 1:]])
+    pk = torch.from_numpy(pk_h.view(np.int64)).cuda()
+    del pk_h
+    s = tpx.Stream(n, pix_epoch0=wl.pix_epoch0, tdc_epoch0=wl.tdc_epoch0)
+    cap = n // 4 + 1024
+    hits = torch.empty((cap, 48), dtype=torch.uint8, device="cuda")
+    fresh = s.get_state()
+    reps = max(1, args.steps // 4)
+    for _ in range(2):
+        s.set_state(fresh)
+        rc, nh, st = s.process_raw(pk, True, hits, cap)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        s.set_state(fresh)
+        rc, nh, st = s.process_raw(pk, True, hits, cap)
+        if rc != 0:
+            raise tpx.TpxError(rc, "tpx_process_stream", s.lib.tpx_last_error().decode())
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    general = s.fallback_count
+    s.close()
+    return dict(workload="c2 with three kept pixels moved behind later shots' pixels (general "
+                         "path: shot of every event, stable 4-bit radix sort by shot, "
+                         "clustering through the permutation)",
+                packets=int(n), events=int(st.n_events), hits=int(nh),
+                general_path_calls=int(general), ms_per_step=ms,
+                events_per_s=st.n_events / (ms * 1e-3))
+
+
 def run_paper_mode(args, wl, name="c2"):
     """The paper's local-maximum hits (tpx_local_maxima) on the decoded
     events of a workload: events resident in HBM, HIP-event timing on the
@@ -698,6 +746,7 @@ def main():
                     help="paced replay speedups over acquisition")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-uneven", action="store_true")
+    ap.add_argument("--no-out-of-order", action="store_true")
     ap.add_argument("--strides", type=int, nargs="+",
                     default=[128, 256, 512, 1024, 2048, 4096],
                     help="segment strides the autotuner tries on the uneven-shot workload")
@@ -826,6 +875,9 @@ def main():
     if not args.no_uneven:
         out["uneven"] = run_uneven(args, wl3)
         log(f"uneven: {out['uneven']}")
+    if not args.no_out_of_order:
+        out["out_of_order"] = run_out_of_order(args, wl)
+        log(f"out of order: {out['out_of_order']}")
     if not args.no_paper_mode:
         out["paper_mode"] = run_paper_mode(args, wl)
         log(f"paper mode: {out['paper_mode']}")

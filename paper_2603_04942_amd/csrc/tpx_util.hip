@@ -243,10 +243,95 @@ __global__ void k_split_scatter(const uint32_t* key, const uint32_t* val, uint64
         val2[d] = val[i];
     }
 }
+// 4-bit digits: blocks of 4,096 pairs (256 threads x 16 consecutive pairs).
+// Pass = count (digit totals of every block, digit-major: cnt[d * nb + b]),
+// exclusive prefix of the counts (every (digit, block) start), scatter: in a
+// block, the exclusive prefix of the per-thread digit counts in digit-major
+// order gives each thread the rank of its first pair of each digit among
+// the block's pairs of that digit; the thread then writes its pairs in order
+// (stable).
+constexpr int kRsThreads = 256, kRsItems = 16, kRsTile = kRsThreads * kRsItems;
+constexpr int kRsBits = 4, kRsDigits = 1 << kRsBits;
+
+__global__ __launch_bounds__(kRsThreads) void k_rs_count(const uint32_t* key, uint64_t n, int sh,
+                                                         uint32_t mask, uint32_t* cnt,
+                                                         uint64_t nb) {
+    __shared__ uint32_t h[kRsDigits];
+    if (threadIdx.x < kRsDigits) h[threadIdx.x] = 0;
+    __syncthreads();
+    const uint64_t b = blockIdx.x, i0 = b * kRsTile + (uint64_t)threadIdx.x * kRsItems;
+    for (int j = 0; j < kRsItems; ++j)
+        if (i0 + j < n) atomicAdd(&h[(key[i0 + j] >> sh) & mask], 1u);
+    __syncthreads();
+    if (threadIdx.x < kRsDigits) cnt[(uint64_t)threadIdx.x * nb + b] = h[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint32_t* key, const uint32_t* val,
+                                                           uint64_t n, int sh, uint32_t mask,
+                                                           const uint32_t* off, uint64_t nb,
+                                                           uint32_t* key2, uint32_t* val2) {
+    __shared__ uint32_t c[kRsDigits * kRsThreads];  // [digit][thread], then cursors
+    __shared__ uint32_t dstart[kRsDigits];           // the block's first position of each digit
+    __shared__ uint32_t tmp[kRsThreads / 64 + 1];
+    const uint32_t t = threadIdx.x;
+    const uint64_t b = blockIdx.x, i0 = b * kRsTile + (uint64_t)t * kRsItems;
+    for (int d = 0; d < kRsDigits; ++d) c[d * kRsThreads + t] = 0;
+    for (int j = 0; j < kRsItems; ++j)
+        if (i0 + j < n) ++c[((key[i0 + j] >> sh) & mask) * kRsThreads + t];
+    __syncthreads();
+    // exclusive prefix over the 4,096 counts in digit-major order: thread t
+    // takes entries [16 t, 16 t + 16)
+    uint32_t v[kRsItems], sum = 0;
+    for (int k = 0; k < kRsItems; ++k) {
+        v[k] = sum;
+        sum += c[t * kRsItems + k];
+    }
+    uint32_t total;
+    const uint32_t base = wg_count_scan<kRsThreads>(sum, tmp, &total);
+    __syncthreads();
+    for (int k = 0; k < kRsItems; ++k) c[t * kRsItems + k] = base + v[k];
+    __syncthreads();
+    if (t < kRsDigits) dstart[t] = c[t * kRsThreads];
+    __syncthreads();
+    // c[d][t] = pairs of the block before thread t's first pair of digit d
+    // (all smaller digits, then digit d in earlier threads); minus the
+    // block's start of digit d it is the rank within digit d; thread t then
+    // advances its own cursor c[d][t]
+    for (int j = 0; j < kRsItems; ++j) {
+        const uint64_t i = i0 + j;
+        if (i >= n) break;
+        const uint32_t k = key[i], d = (k >> sh) & mask;
+        const uint32_t r = c[d * kRsThreads + t] - dstart[d];
+        ++c[d * kRsThreads + t];
+        const uint64_t dst = (uint64_t)off[(uint64_t)d * nb + b] + r;
+        key2[dst] = k;
+        val2[dst] = val[i];
+    }
+}
+
 void radix_sort_pairs(uint32_t* key, uint32_t* val, uint32_t* key2, uint32_t* val2,
                       uint32_t* flags, uint32_t* scan, uint32_t* block_tmp, uint64_t n, int bits,
                       hipStream_t s, uint32_t** key_out, uint32_t** val_out) {
-    for (int b = 0; b < bits && n > 1; ++b) {
+    // 4-bit passes while the digit counts fit the buffers (flags: n + 1
+    // words, scan: n + 2), else (fewer than 32 pairs) one bit at a time
+    const uint64_t nb = (n + kRsTile - 1) / kRsTile;
+    const bool wide = n >= 32 && (uint64_t)kRsDigits * nb + 1 <= n + 1;
+    for (int b = 0; wide && b < bits; b += kRsBits) {
+        const int w = bits - b < kRsBits ? bits - b : kRsBits;
+        const uint32_t mask = (1u << w) - 1u;
+        hipLaunchKernelGGL(k_rs_count, dim3((unsigned)nb), dim3(kRsThreads), 0, s, key, n, b, mask,
+                           flags, nb);
+        launch_scan_u32(flags, scan, (uint64_t)kRsDigits * nb, nullptr, block_tmp, s);
+        hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)nb), dim3(kRsThreads), 0, s, key, val, n, b,
+                           mask, scan, nb, key2, val2);
+        uint32_t* t = key;
+        key = key2;
+        key2 = t;
+        t = val;
+        val = val2;
+        val2 = t;
+    }
+    for (int b = 0; !wide && b < bits && n > 1; ++b) {
         hipLaunchKernelGGL(k_split_flags, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, key, n, b,
                            flags);
         launch_scan_u32(flags, scan, n, nullptr, block_tmp, s);

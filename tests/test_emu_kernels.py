@@ -108,6 +108,25 @@ def test_stream_kernels(emu, orc, kernel, name, shots, chunk):
         _assert_hits(hits, ref)
 
 
+def test_stream_out_of_order_sort(emu, orc):
+    """Kept pixels reported after pixels of later shots: the stream takes the
+    general path, whose stable 4-bit radix sort by shot (count, prefix,
+    scatter per 4,096 pairs) must reproduce the oracle's shot order."""
+    w = synth.make_config("c1", n_shots=60)
+    pk = w.packets.copy()
+    kept = np.nonzero(w.kept_mask())[0]
+    moves = [(int(kept[np.argmax(w.shot[kept] == a)]), int(kept[np.argmax(w.shot[kept] == b)]))
+             for a, b in ((10, 12), (30, 33), (45, 46))]
+    for i, j in sorted(moves, reverse=True):      # later moves first: indices stay valid
+        pk = np.concatenate([pk[:i], pk[i + 1:j + 1], pk[i:i + 1], pk[j + 1:]])
+    kw = dict(pix_epoch0=w.pix_epoch0, tdc_epoch0=w.tdc_epoch0)
+    ref, _ = orc.run(pk, **kw)
+    st, hits, errs = emu.run_stream(pk, 1 << 22, kernel=1, persistent=0, preempt=100, seed=9, **kw)
+    assert errs == ""
+    assert st == 0
+    _assert_hits(hits, ref)
+
+
 @pytest.mark.parametrize("persistent", [0, 1])
 @pytest.mark.parametrize("name,shots,chunks", [("c1", 60, (1500, 40000)), ("c5", 8, (8192, 3000)),
                                                ("c3", 12, (30000, 1 << 22))])

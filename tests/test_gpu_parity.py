@@ -268,6 +268,28 @@ def test_stream_out_of_order_takes_general_path(tpx, orc):
     assert_hits_match(h, ref)
 
 
+def test_stream_out_of_order_at_scale(tpx, orc):
+    """Out-of-order pixels in a 300-shot c2 stream (about 190,000 events):
+    the general path sorts every event by shot with the 4-bit radix sort
+    (several 4,096-pair blocks and five passes) and must give the oracle's
+    hits."""
+    w = synth.make_config("c2", n_shots=300)
+    pk = w.packets.copy()
+    kept = np.nonzero(w.kept_mask())[0]
+    moves = []
+    for a_shot, b_shot in ((10, 12), (100, 101), (250, 254)):
+        moves.append((int(kept[np.argmax(w.shot[kept] == a_shot)]),
+                      int(kept[np.argmax(w.shot[kept] == b_shot)])))
+    for i, j in sorted(moves, reverse=True):      # later moves first: indices stay valid
+        pk = np.concatenate([pk[:i], pk[i + 1:j + 1], pk[i:i + 1], pk[j + 1:]])
+    kw = dict(pix_epoch0=w.pix_epoch0, tdc_epoch0=w.tdc_epoch0)
+    ref, _ = orc.run(pk, **kw)
+    s = tpx.Stream(pk.size, **kw)
+    h, _ = s.process(pk, flush=True)
+    assert s.fallback_count == 1
+    assert_hits_match(h, ref)
+
+
 def test_stream_resume_from_checkpoint(tpx, orc):
     w = synth.make_config("c5", n_shots=80)
     kw = dict(pix_epoch0=w.pix_epoch0, tdc_epoch0=w.tdc_epoch0)
