@@ -52,18 +52,41 @@ __global__ void k_patch_clear(uint32_t* acc, uint64_t n_hits) {
 
 // one thread per event: find its hit by (shot, label) in the (shot, label)
 // ordered hit list, then add its ToT and fold its ToA into the pixel's cell
-__global__ void k_patch_accum(tpx_events ev, const uint32_t* labels, uint64_t n_ev,
-                              const tpx_hit* hits, uint64_t n_hits, uint32_t* acc, int* err) {
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_ev) return;
-    const uint64_t key = ((uint64_t)ev.shot[i] << 32) | labels[i];
-    uint64_t lo = 0, hi = n_hits;
+// the hit of (shot, label) key in the (shot, label)-ordered hits: first
+// index whose key is not below it
+__device__ inline uint64_t hit_lower_bound(const tpx_hit* hits, uint64_t lo, uint64_t hi,
+                                           uint64_t key) {
     while (lo < hi) {
         const uint64_t mid = (lo + hi) >> 1;
         const uint64_t k = (hits[mid].shot << 32) | hits[mid].label;
         if (k < key) lo = mid + 1;
         else hi = mid;
     }
+    return lo;
+}
+
+// One thread per event.  The events of a hit usually sit together, so the
+// first active lane of the wave searches the whole hit list and every lane
+// tries that hit and the next two before its own search.
+__global__ void k_patch_accum(tpx_events ev, const uint32_t* labels, uint64_t n_ev,
+                              const tpx_hit* hits, uint64_t n_hits, uint32_t* acc, int* err) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_ev) return;
+    const uint64_t key = ((uint64_t)ev.shot[i] << 32) | labels[i];
+    const int first = __builtin_amdgcn_readfirstlane((int)__lane_id());
+    const uint64_t lead_key = __shfl(key, first, 64);
+    uint64_t lo = 0;
+    if ((int)__lane_id() == first) lo = hit_lower_bound(hits, 0, n_hits, lead_key);
+    const uint64_t guess = __shfl(lo, first, 64);
+    bool found = false;
+    for (uint64_t g = guess; g < guess + 3 && g < n_hits; ++g) {
+        if (((hits[g].shot << 32) | hits[g].label) == key) {
+            lo = g;
+            found = true;
+            break;
+        }
+    }
+    if (!found) lo = hit_lower_bound(hits, 0, n_hits, key);
     if (lo >= n_hits || ((hits[lo].shot << 32) | hits[lo].label) != key) {
         atomicOr(err, 1);
         return;
