@@ -206,10 +206,15 @@ def run_latency(args):
                 n_ev += st.n_events
             return np.array(lat), n_ev, time.perf_counter() - t0
 
+        # segment stride for this chunk size: the autotuner on the first
+        # chunk (small chunks favour short segments)
+        q_best, _, q_sweep = s.autotune(pk[:chunk], False, [128, 256, 512, 1024], hits, chunk,
+                                        reps=3)
         fresh = s.get_state()
         replay(min(len(starts), 8), 0)           # warm-up
         lat, n_ev, span = replay(len(starts), 0)
         row = dict(chunk_packets=chunk, chunk_kib=chunk * 8 // 1024, chunks=len(starts),
+                   stride=q_best, stride_sweep_ms={q: round(v, 4) for (_, q), v in q_sweep.items()},
                    p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
                    events_per_s=n_ev / span, replay_capacity=acq_s / span, paced={})
         for speed in args.latency_speeds:
@@ -223,8 +228,8 @@ def run_latency(args):
         s.set_patches(False)
         s.close()
         del hits
-        row["paced_batched"] = batched_replays(args, tpx, w, pk, chunk, pk_rate)
-        row["paced_batched_threaded"] = threaded_replays(args, tpx, w, pk, chunk, pk_rate)
+        row["paced_batched"] = batched_replays(args, tpx, w, pk, chunk, pk_rate, q_best)
+        row["paced_batched_threaded"] = threaded_replays(args, tpx, w, pk, chunk, pk_rate, q_best)
         out["sizes"].append(row)
     return out
 
@@ -265,7 +270,7 @@ def refined_replay(args, tpx, s, fresh, pk, chunk, hits, starts):
                 hits_per_s=n_h / span, replay_capacity=args.latency_shots * 1e-3 / span)
 
 
-def batched_replays(args, tpx, w, pk, chunk, pk_rate):
+def batched_replays(args, tpx, w, pk, chunk, pk_rate, q):
     """Paced replays through tpx_service from one thread: every chunk released
     so far is admitted, then one run takes all of them (up to the batch
     limit); when chunks arrive faster than one call per chunk can finish,
@@ -284,6 +289,7 @@ def batched_replays(args, tpx, w, pk, chunk, pk_rate):
     for speed in args.latency_speeds:
         lim = max(1, min(len(starts), int(2.0 * pk_rate * speed / chunk)))
         sv = tpx.Service(max_batch, pix_epoch0=w.pix_epoch0, tdc_epoch0=w.tdc_epoch0)
+        sv.set_segment(q)
         ptrs = [ctypes.c_void_p(pk[a:a + chunk].data_ptr()) for a in starts[:lim]]
         sizes = [min(chunk, n_pk - a) for a in starts[:lim]]
         hstream = tpx._stream(torch)
@@ -320,7 +326,7 @@ def batched_replays(args, tpx, w, pk, chunk, pk_rate):
     return res
 
 
-def threaded_replays(args, tpx, w, pk, chunk, pk_rate):
+def threaded_replays(args, tpx, w, pk, chunk, pk_rate, q):
     """Paced replays through tpx_service driven by the library's native
     producer (tpx_service_replay): a producer thread inside the library admits
     chunk k at its release (its copy goes on the service's own stream and
@@ -335,6 +341,7 @@ def threaded_replays(args, tpx, w, pk, chunk, pk_rate):
         n_chunks = -(-n_pk // chunk)
         lim = max(1, min(n_chunks, int(2.0 * pk_rate * speed / chunk)))
         sv = tpx.Service(max_batch, pix_epoch0=w.pix_epoch0, tdc_epoch0=w.tdc_epoch0)
+        sv.set_segment(q)
         lat, runs = sv.replay(pk[:min(n_pk, lim * chunk)], chunk, pk_rate * speed,
                               hit_cap=2 * max_batch)
         sv.close()

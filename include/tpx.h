@@ -354,6 +354,8 @@ tpx_status tpx_service_run(tpx_service* sv, int flush, tpx_hit* hits, size_t hit
 void tpx_service_destroy(tpx_service* sv);
 /*   tpx_service_device_bytes  device memory the service holds (its stream,
  *                       ring and staging buffer).
+ *   tpx_service_set_segment  segment stride of the service's stream (as
+ *                       tpx_stream_set_segment); not while a run is on the GPU.
  *   tpx_service_replay  paced replay with a native producer thread: chunk k
  *                       (chunk words of the device-resident stream pk[n]) is
  *                       submitted when its last word would have been acquired
@@ -365,6 +367,7 @@ void tpx_service_destroy(tpx_service* sv);
  *                       service must hold no unprocessed chunks.  hits /
  *                       hit_cap receive each run's hits in turn. */
 size_t tpx_service_device_bytes(const tpx_service* sv);
+tpx_status tpx_service_set_segment(tpx_service* sv, uint32_t q);
 tpx_status tpx_service_replay(tpx_service* sv, const uint64_t* pk, size_t n, size_t chunk,
                               double pkts_per_s, tpx_hit* hits, size_t hit_cap, float* lat_ms_h,
                               size_t lat_cap, size_t* n_chunks_h, uint64_t* n_runs_h,

@@ -76,6 +76,7 @@ EXPORTS = ("tpx_params_default", "tpx_unwrap_state_init", "tpx_workspace_bytes",
            "tpx_stream_patch_workspace_bytes", "tpx_stream_patches", "tpx_stream_set_patches",
            "tpx_stream_kernel_count", "tpx_stream_kernel_name", "tpx_stream_set_kernel",
            "tpx_stream_get_kernel", "tpx_stream_set_persistent", "tpx_stream_get_persistent",
+           "tpx_service_set_segment",
            "tpx_cluster_static", "tpx_cluster_static_max_events",
            "tpx_walk_fit", "tpx_walk_fit_workspace_bytes", "tpx_stream_device_bytes",
            "tpx_service_device_bytes", "tpx_service_replay", "tpx_server_create", "tpx_server_open",
@@ -171,6 +172,8 @@ def load(path=LIB_PATH):
     lib.tpx_stream_set_kernel.restype = I
     lib.tpx_stream_get_kernel.argtypes = [P]
     lib.tpx_stream_get_kernel.restype = ctypes.c_int
+    lib.tpx_service_set_segment.argtypes = [P, ctypes.c_uint32]
+    lib.tpx_service_set_segment.restype = I
     lib.tpx_stream_set_persistent.argtypes = [P, ctypes.c_int]
     lib.tpx_stream_set_persistent.restype = I
     lib.tpx_stream_get_persistent.argtypes = [P]
@@ -535,6 +538,10 @@ class Service:
         ring = 4 * max_batch_pkts if ring_pkts is None else ring_pkts
         _check(self.lib.tpx_service_create(ctypes.byref(self.p), max_batch_pkts, ring,
                                            ctypes.byref(self.h)), "tpx_service_create")
+
+    def set_segment(self, q):
+        """Segment stride of the service's stream."""
+        _check(self.lib.tpx_service_set_segment(self.h, int(q)), "tpx_service_set_segment")
 
     def submit(self, chunk):
         """Admit a chunk (device tensor or numpy uint64); returns its number."""

@@ -218,6 +218,12 @@ void tpx_service_destroy(tpx_service* sv) {
     if (sv) free_service(sv);
 }
 
+tpx_status tpx_service_set_segment(tpx_service* sv, uint32_t q) {
+    if (!sv) return tpx::report(TPX_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(sv->mu);
+    return tpx_stream_set_segment(sv->st, q);
+}
+
 size_t tpx_service_device_bytes(const tpx_service* sv) {
     return sv ? tpx_stream_device_bytes(sv->st) + (sv->ring_cap + sv->max_batch) * 8 : 0;
 }

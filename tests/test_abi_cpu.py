@@ -106,4 +106,5 @@ def test_learned_and_tuning_argument_errors_need_no_gpu():
     assert lib.tpx_stream_get_kernel(None) == -2
     assert lib.tpx_stream_set_persistent(None, 4) == tpx.EINVAL
     assert lib.tpx_stream_get_persistent(None) == -1
+    assert lib.tpx_service_set_segment(None, 256) == tpx.EINVAL
     assert lib.tpx_stream_set_patches(None, 1) == tpx.EINVAL
