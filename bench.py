@@ -206,15 +206,23 @@ def run_latency(args):
                 n_ev += st.n_events
             return np.array(lat), n_ev, time.perf_counter() - t0
 
-        # segment stride for this chunk size: the autotuner on the first
-        # chunk (small chunks favour short segments)
-        q_best, _, q_sweep = s.autotune(pk[:chunk], False, [128, 256, 512, 1024], hits, chunk,
-                                        reps=3)
+        # segment stride for this chunk size: the one with the lowest p99 of
+        # a back-to-back replay of (up to 1,500 of) the chunks
         fresh = s.get_state()
+        q_sweep = {}
+        for q in (256, 512, 1024):
+            s.set_segment(q)
+            replay(min(len(starts), 8), 0)
+            lat_q, _, _ = replay(min(len(starts), 1500), 0)
+            q_sweep[q] = (float(np.percentile(lat_q, 50)), float(np.percentile(lat_q, 99)))
+        q_best = min(q_sweep, key=lambda q: q_sweep[q][1])
+        s.set_segment(q_best)
         replay(min(len(starts), 8), 0)           # warm-up
         lat, n_ev, span = replay(len(starts), 0)
         row = dict(chunk_packets=chunk, chunk_kib=chunk * 8 // 1024, chunks=len(starts),
-                   stride=q_best, stride_sweep_ms={q: round(v, 4) for (_, q), v in q_sweep.items()},
+                   stride=q_best,
+                   stride_sweep_p50_p99_ms={q: (round(a, 4), round(b, 4))
+                                            for q, (a, b) in q_sweep.items()},
                    p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
                    events_per_s=n_ev / span, replay_capacity=acq_s / span, paced={})
         for speed in args.latency_speeds:
