@@ -840,7 +840,7 @@ tpx_status stream_persistent(tpx_stream* s, const uint64_t* chunk, uint64_t n, i
     if (hipMemcpyAsync(s->chunk_args, s->chunk_args_h, sizeof(ChunkArgs), hipMemcpyHostToDevice,
                        hs) != hipSuccess)
         return fail(TPX_EHIP, "argument copy failed");
-    launch_stream_chunk(p, s->chunk_args, 2 * s->n_cu, hs);
+    launch_stream_chunk(p, s->chunk_args, s->n_cu, hs);
     for (int i = 5; i <= 7; ++i) mark(s, i, hs);
     tpx_status rc = read_res(s->res, s->res_h, hs);
     if (rc == TPX_OK && s->timing)
