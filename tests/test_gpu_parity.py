@@ -139,6 +139,24 @@ def test_stream_chunked(tpx, orc, seed):
     assert s.fallback_count == 0
 
 
+def test_stream_persistent_near_the_tile_limit(tpx, orc):
+    """A chunk of about 500 tiles in one persistent launch (one tile per
+    thread in the prefix item, hundreds of segments taken by ticket), and the
+    same stream as chunks above the limit, which take the separate launches."""
+    w = synth.make_config("c2", n_shots=3200)
+    kw = dict(pix_epoch0=w.pix_epoch0, tdc_epoch0=w.tdc_epoch0)
+    ref, _ = orc.run(w.packets, **kw)
+    tiles = -(-w.n_packets // 4096)
+    _say(f"persistent limit: {w.n_packets} packets, {tiles} tiles")
+    assert 400 < tiles <= 512
+    h, _ = tpx.process_stream(w.packets, persistent=512, **kw)
+    assert_hits_match(h, ref)
+    s = tpx.Stream(w.n_packets, persistent=tiles - 1, **kw)   # every chunk above the limit
+    h2, _ = s.process(w.packets, flush=True)
+    s.close()
+    assert h2.tobytes() == h.tobytes()
+
+
 @pytest.mark.parametrize("persistent", [True, False])
 def test_stream_ends_with_empty_flush(tpx, orc, persistent):
     """A stream whose last call flushes no new words: the open shots carried
