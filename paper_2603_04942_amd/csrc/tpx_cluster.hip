@@ -1257,7 +1257,9 @@ struct FusedCfg {
     static constexpr int kSlots = 256 << kYB;      // u16 list heads
     static constexpr uint32_t kYMask = (1u << kYB) - 1u;
     static constexpr int kYHB = 8 - kYB;           // bits of y above the slot's
-    static constexpr int kGShift = 16 + kYHB;      // group start above the time and y bits
+    // key: time (bits 0-15), a zero guard bit (16), then hi() from bit 17
+    static constexpr int kHShift = 17;
+    static constexpr int kGShift = kHShift + kYHB;  // group start above the time and y bits
     static constexpr int kE = kSeg / kNT;          // events per thread
     // edges kept in registers per event (more are found again by walking the
     // slot lists in every round): fewer where a thread holds many events
@@ -1282,6 +1284,16 @@ struct FusedCfg {
     __device__ static uint32_t slot(uint32_t x, uint32_t y) { return ((y & kYMask) << 8) | x; }
     // key bits above the time: group start and the high bits of y
     __device__ static uint32_t hi(uint32_t gs, uint32_t y) { return (gs << kYHB) | (y >> kYB); }
+    // Offset that turns the neighbour test into one comparison: the key kj
+    // has hi() = h and a time within dt of t exactly when
+    // kj + off(h, t, dt) <= 2 dt (unsigned).  With equal hi() the sum is
+    // tj - t + dt, in [0, 2 dt] exactly for the window and wrapped above it
+    // when tj < t - dt; with unequal hi() it differs by a nonzero multiple
+    // of 2^17 (mod 2^32) from a value in [-65535, 131070], which the guard
+    // bit keeps out of [0, 2 dt] for any dt < 65536.
+    __device__ static uint32_t off(uint32_t h, uint32_t t, uint32_t dt) {
+        return dt - ((h << kHShift) | t);
+    }
 };
 
 // Global accumulators of component c of the segment starting at e0: 8 words
@@ -1466,7 +1478,7 @@ __device__ __forceinline__ void fused_segment(const ClusterArgs& a, uint32_t k, 
                 const uint32_t gs = (goff_lds ? goff[g - sg.g_lo] : a.grp_off[g]) - (uint32_t)e0;
                 const uint64_t pk = a.ev[p];
                 const uint32_t x = ev_x(pk), y = ev_y(pk);
-                key[i] = (ev_t(pk) & 0xFFFFu) | (C::hi(gs, y) << 16);
+                key[i] = (ev_t(pk) & 0xFFFFu) | (C::hi(gs, y) << C::kHShift);
                 xyt[i] = x | (y << 8) | (ev_tot(pk) << 16);
                 par[i] = i;
                 // push i on its slot's list: swap it into the slot's half of
@@ -1515,7 +1527,9 @@ __device__ __forceinline__ void fused_segment(const ClusterArgs& a, uint32_t k, 
             const int x = (int)(xy & 255u), y = (int)((xy >> 8) & 255u);
             const uint32_t ki = key[i];
             const uint32_t ti = ki & 0xFFFFu, gs = ki >> C::kGShift;
-            const uint32_t want_up = C::hi(gs, (uint32_t)(y - 1)), want_row = C::hi(gs, (uint32_t)y);
+            const uint32_t off_up = C::off(C::hi(gs, (uint32_t)(y - 1)), ti, dt);
+            const uint32_t off_row = C::off(C::hi(gs, (uint32_t)y), ti, dt);
+            const uint32_t span = 2u * dt;
             constexpr int kDx[5] = {-1, 0, 1, -1, 0};
             constexpr int kDy[5] = {-1, -1, -1, 0, 0};
             uint32_t head[5];
@@ -1540,17 +1554,17 @@ __device__ __forceinline__ void fused_segment(const ClusterArgs& a, uint32_t k, 
                 n2[s] = hn[s] == kNone16 ? kNone16 : nxt[j];
             }
             uint32_t m = i, c = 0;
+            // (events of other slots are never i itself; in its own slot
+            // only earlier events count)
             auto take = [&](uint32_t j, uint32_t kj, int s) {
-                const uint32_t w = s < 3 ? want_up : want_row;
-                if ((s < 4 || j < i) && j != i && (kj >> 16) == w &&
-                    absdiff(kj & 0xFFFFu, ti) <= dt) {
+                if ((s < 4 || j < i) && kj + (s < 3 ? off_up : off_row) <= span) {
                     if (j < m) m = j;
-                    if (j > i) atomicMin(par + j, i);
-                    const uint32_t wd = c >> 1, sh16 = (c & 1u) * 16u;
-                    if (c < (uint32_t)kEd) {
+                    if (s < 4 && j > i) atomicMin(par + j, i);
+                    // shift register of 16-bit links: the newest at the
+                    // bottom, the oldest dropped past kEd
 #pragma unroll
-                        for (int w = 0; w < kNbW; ++w) nb[q][w] |= wd == (uint32_t)w ? j << sh16 : 0u;
-                    }
+                    for (int w = kNbW - 1; w > 0; --w) nb[q][w] = (nb[q][w] << 16) | (nb[q][w - 1] >> 16);
+                    nb[q][0] = (nb[q][0] << 16) | j;
                     ++c;
                 }
             };
@@ -1629,12 +1643,11 @@ __device__ __forceinline__ void fused_segment(const ClusterArgs& a, uint32_t k, 
                     for (int s = 0; s < 5; ++s) {
                         const int nx = x + (s == 3 ? -1 : s == 4 ? 0 : s - 1), ny = y - (s < 3 ? 1 : 0);
                         if (nx < 0 || nx > 255 || ny < 0) continue;
-                        const uint32_t w = C::hi(gs, (uint32_t)ny);
+                        const uint32_t o = C::off(C::hi(gs, (uint32_t)ny), ti, dt);
                         uint32_t j = head16[C::slot((uint32_t)nx, (uint32_t)ny)], steps = 0;
                         while (j != kNone16) {
                             const uint32_t kj = key[j];
-                            if ((s < 4 || j < i) && j != i && (kj >> 16) == w &&
-                                absdiff(kj & 0xFFFFu, ti) <= dt) {
+                            if ((s < 4 || j < i) && kj + o <= 2u * dt) {
                                 const uint32_t r2 = ald(par + j);
                                 if (r2 != ri) {
                                     atomicMin(par + (r2 < ri ? ri : r2), r2 < ri ? r2 : ri);
