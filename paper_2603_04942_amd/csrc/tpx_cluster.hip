@@ -1242,9 +1242,10 @@ namespace tpx {
 //      so every edge is seen once, keeps up to 8 of them in registers and
 //      lowers the parents of both ends to the smaller end (LDS atomic
 //      minimum): a min-neighbour forest;
-//   3. rounds of pointer jumping and root hooking over the kept edges until
-//      no edge joins two trees (the smallest position of each component, its
-//      label, is then every member's parent);
+//   3. pointer jumping, one pass that joins the two trees of every kept
+//      edge by chains of atomic minima on tree roots, pointer jumping again
+//      (the smallest position of each component, its label, is then every
+//      member's parent);
 //   4. ranks of the roots in position order;
 //   5. moments per component (LDS atomics);
 //   6. hits, staged.
@@ -1514,7 +1515,7 @@ __device__ __forceinline__ void fused_segment(const ClusterArgs& a, uint32_t k, 
         // The edges (up to C::kEdges per event) stay in registers.
         constexpr int kEd = C::kEdges, kNbW = kEd / 2;
         uint32_t nb[kE][kNbW];
-        uint32_t meta[kE];  // edges found (bits 0-7), live kept edges (8-15)
+        uint32_t meta[kE];  // edges found (at most 255 counted)
         bool ok = true;
 #pragma unroll
         for (int q = 0; q < kE; ++q) {
@@ -1589,83 +1590,105 @@ __device__ __forceinline__ void fused_segment(const ClusterArgs& a, uint32_t k, 
                     }
                 }
             }
-            meta[q] = (c < 255 ? c : 255) |
-                      ((c > (uint32_t)kEd ? (1u << kEd) - 1u : (1u << c) - 1u) << 8);
+            meta[q] = c < 255 ? c : 255;
             if (m < i) atomicMin(par + i, m);
         }
         if (!ok) atomicOr(err, (unsigned long long)kErrLoopChain);
         __syncthreads();
-        // 3. rounds: pointer jumping (every event points at its tree's root),
-        // then for every kept edge whose ends lie in different trees the
-        // larger root is pointed at the smaller (atomic minimum: parents only
-        // ever decrease, so the forest stays a forest); an edge once inside
-        // a tree stays inside and is dropped.  A round with no such edge
-        // ends it.  An event with more edges than it keeps walks its lists in
-        // every round.
-        for (uint32_t round = 0;; ++round) {
+        // 3. pointer jumping: every event then points at its tree's root
+        // (a "jump root").  Then one pass over the edges: for an edge whose
+        // ends read different parents h > l, an atomic minimum points h at l;
+        // the old parent it returns is either h (h was a root: joined), l
+        // (already joined) or a third node o, also a jump root, which is then
+        // joined the same way with l (h -> l may have displaced h -> o, so o
+        // and l must meet).  The larger node of each step is smaller than
+        // the last, so every chain ends, and when all have ended every edge
+        // joins one tree; only jump roots ever change their parent, and
+        // parents only decrease, so the trees stay a forest whose roots are
+        // the smallest positions of their components.  An event with more
+        // edges than it keeps walks its lists instead.  A last pointer
+        // jumping leaves every event pointing at its root.
 #pragma unroll
-            for (int q = 0; q < kE; ++q) {
-                const uint32_t i = tid + q * kNT;
-                if (i >= n) continue;
-                uint32_t p = ald(par + i), steps = 0;
-                for (uint32_t nx; p != (nx = ald(par + p)) && ++steps <= n;) p = nx;
-                ast(par + i, p);
+        for (int q = 0; q < kE; ++q) {
+            const uint32_t i = tid + q * kNT;
+            if (i >= n) continue;
+            uint32_t p = ald(par + i), steps = 0;
+            for (uint32_t nx; p != (nx = ald(par + p)) && ++steps <= n;) p = nx;
+            ast(par + i, p);
+        }
+        __syncthreads();
+        bool loop_err = false;
+        auto join = [&](uint32_t u, uint32_t v) {
+            uint32_t h = u < v ? v : u, l = u < v ? u : v;
+            for (uint32_t st = 0;; ++st) {
+                const uint32_t o = atomicMin(par + h, l);
+                if (o == h || o == l) break;
+                if (st > n) {
+                    loop_err = true;
+                    break;
+                }
+                h = o < l ? l : o;
+                l = o < l ? o : l;
             }
-            __syncthreads();
-            bool hooked = false;
+        };
+        uint32_t walks = 0;  // bit q: event tid + q kNT walks its lists
 #pragma unroll
-            for (int q = 0; q < kE; ++q) {
-                const uint32_t i = tid + q * kNT;
-                const uint32_t cq = meta[q] & 0xFFu;
-                if (i >= n || ((meta[q] >> 8) == 0 && cq <= (uint32_t)kEd)) continue;
-                const uint32_t ri = ald(par + i);
-                uint32_t rj[kEd];
-#pragma unroll
-                for (int t = 0; t < kEd; ++t) {
-                    const uint32_t j = (nb[q][t >> 1] >> ((t & 1) * 16)) & 0xFFFFu;
-                    rj[t] = (meta[q] >> (8 + t)) & 1u ? ald(par + j) : ri;
-                }
-#pragma unroll
-                for (int t = 0; t < kEd; ++t) {
-                    if (rj[t] == ri) {
-                        meta[q] &= ~(1u << (8 + t));
-                    } else {
-                        const uint32_t lo = rj[t] < ri ? rj[t] : ri, hi = rj[t] < ri ? ri : rj[t];
-                        atomicMin(par + hi, lo);
-                        hooked = true;
-                    }
-                }
-                if (cq > (uint32_t)kEd) {
-                    const uint32_t xy = xyt[i];
-                    const int x = (int)(xy & 255u), y = (int)((xy >> 8) & 255u);
-                    const uint32_t ki = key[i];
-                    const uint32_t ti = ki & 0xFFFFu, gs = ki >> C::kGShift;
-                    for (int s = 0; s < 5; ++s) {
-                        const int nx = x + (s == 3 ? -1 : s == 4 ? 0 : s - 1), ny = y - (s < 3 ? 1 : 0);
-                        if (nx < 0 || nx > 255 || ny < 0) continue;
-                        const uint32_t o = C::off(C::hi(gs, (uint32_t)ny), ti, dt);
-                        uint32_t j = head16[C::slot((uint32_t)nx, (uint32_t)ny)], steps = 0;
-                        while (j != kNone16) {
-                            const uint32_t kj = key[j];
-                            if ((s < 4 || j < i) && kj + o <= 2u * dt) {
-                                const uint32_t r2 = ald(par + j);
-                                if (r2 != ri) {
-                                    atomicMin(par + (r2 < ri ? ri : r2), r2 < ri ? r2 : ri);
-                                    hooked = true;
-                                }
-                            }
-                            if (++steps > n) break;
-                            j = nxt[j];
-                        }
-                    }
-                }
+        for (int q = 0; q < kE; ++q) {
+            const uint32_t i = tid + q * kNT;
+            if (i >= n) continue;
+            const uint32_t cq = meta[q];
+            if (cq > (uint32_t)kEd) {
+                walks |= 1u << q;
+                continue;
             }
-            if (!__syncthreads_or(hooked)) break;
-            if (round >= kMaxRounds) {  // far more rounds than any forest needs
-                if (tid == 0) atomicOr(err, (unsigned long long)kErrLoopUnite);
-                break;
+            const uint32_t ri = ald(par + i);
+            uint32_t rj[kEd];
+#pragma unroll
+            for (int t = 0; t < kEd; ++t) {
+                const uint32_t j = (nb[q][t >> 1] >> ((t & 1) * 16)) & 0xFFFFu;
+                rj[t] = (uint32_t)t < cq ? ald(par + j) : ri;
+            }
+#pragma unroll
+            for (int t = 0; t < kEd; ++t)
+                if (rj[t] != ri) join(ri, rj[t]);
+        }
+        // (one copy of the walk for all q: it reads everything from LDS)
+#pragma unroll 1
+        for (int q = 0; q < kE; ++q) {
+            const uint32_t i = tid + q * kNT;
+            if (!((walks >> q) & 1u)) continue;
+            const uint32_t ri = ald(par + i);
+            const uint32_t xy = xyt[i];
+            const int x = (int)(xy & 255u), y = (int)((xy >> 8) & 255u);
+            const uint32_t ki = key[i];
+            const uint32_t ti = ki & 0xFFFFu, gs = ki >> C::kGShift;
+            for (int s = 0; s < 5; ++s) {
+                const int nx = x + (s == 3 ? -1 : s == 4 ? 0 : s - 1), ny = y - (s < 3 ? 1 : 0);
+                if (nx < 0 || nx > 255 || ny < 0) continue;
+                const uint32_t o = C::off(C::hi(gs, (uint32_t)ny), ti, dt);
+                uint32_t j = head16[C::slot((uint32_t)nx, (uint32_t)ny)], steps = 0;
+                while (j != kNone16) {
+                    const uint32_t kj = key[j];
+                    if ((s < 4 || j < i) && kj + o <= 2u * dt) {
+                        const uint32_t r2 = ald(par + j);
+                        if (r2 != ri) join(ri, r2);
+                    }
+                    if (++steps > n) break;
+                    j = nxt[j];
+                }
             }
         }
+        if (loop_err) atomicOr(err, (unsigned long long)kErrLoopUnite);
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kE; ++q) {
+            const uint32_t i = tid + q * kNT;
+            if (i >= n) continue;
+            uint32_t p = ald(par + i), steps = 0;
+            for (uint32_t nx; p != (nx = ald(par + p)) && ++steps <= n;) p = nx;
+            ast(par + i, p);
+        }
+        __syncthreads();
         // every parent is now its root; the image region becomes the accumulators
         for (int c = tid; c < C::kHitCap; c += kNT) {
             aW[c] = 0;
