@@ -326,7 +326,12 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, uint32_t tile_s
     uint32_t nkeep = 0, npre = 0, ncut = 0, nlate = 0;
     uint32_t first_s = kNo, last_s = 0;
     bool sorted = true;
+    // the slice interval [h_lo, h_hi) of the last search, in registers:
+    // consecutive pixels mostly fall in the same shot, so most need no LDS
+    // read (h_lo = 0 stands for "no entry before", h_hi = ~0 for "no entry
+    // after" within the slice)
     uint32_t hint = 0;
+    uint64_t h_lo = 0, h_hi = len ? slice[0] : ~0ull;
 #pragma unroll
     for (int j = 0; j < kItems; ++j) {
         sv[j] = kNo;
@@ -357,10 +362,13 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, uint32_t tile_s
         const bool above = has_above && t >= slice[len];
         if (!below && !above) {
             // entries before the slice are <= t, entries after it are > t
-            const bool ok = (hint == 0 || slice[hint - 1] <= t) && (hint == len || t < slice[hint]);
-            if (!ok) hint = (uint32_t)upper_bound_u64(slice, 0, len, t);
+            if (!(h_lo <= t && t < h_hi)) {
+                hint = (uint32_t)upper_bound_u64(slice, 0, len, t);
+                h_lo = hint ? slice[hint - 1] : 0;
+                h_hi = hint < len ? slice[hint] : ~0ull;
+            }
             ub = s_lo + hint;
-            trig = hint ? slice[hint - 1] : 0;
+            trig = h_lo;
         } else {
             ub = upper_bound_u64(a.tab, 0, n_tab, t);
             trig = ub ? a.tab[ub - 1] : 0;
