@@ -30,8 +30,20 @@ constexpr size_t kOffW1 = 0, kOffB1 = kOffW1 + (size_t)kHid * kIn, kOffW2 = kOff
 static_assert(kNParam == 93192, "parameter count of the 98-256-256-8 network");
 constexpr size_t kFwdChunk = 65536;  // rows per forward pass in tpx_mlp_forward
 
-typedef short s16x4 __attribute__((ext_vector_type(4)));
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// gfx950's 16x16x32 bfloat16 MFMA: C[16][16] += A[16][32] B[32][16].  Lane
+// l holds row (A) or column (B) l % 16 and eight k of group l / 16; any
+// assignment of the 32 k to (group, element) gives the same product as long
+// as A and B use the same one, and every caller here gives lane l the k
+// 8 (l / 16) .. +7 in order.  Result lane l holds C[4 (l / 16) + r][l % 16],
+// r = 0..3.
+__device__ __forceinline__ f32x4 mfma32(s16x8 a, s16x8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                   __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
 
 // fp32 -> bfloat16, round to nearest, ties to even (finite inputs)
 __device__ __forceinline__ uint16_t to_bf16(float f) {
@@ -287,10 +299,8 @@ __host__ inline int vec_width(const uint16_t* p, int64_t s_row, int64_t s_k, int
 }
 
 // 256 threads = 4 waves in 2 x 2; each wave owns a 32 x (kTN / 2) block of
-// the 64 x kTN tile as 2 x (kTN / 32) MFMA 16x16x16 blocks.  Operand layout
-// of the MFMA: lane l holds A[l % 16][4 (l / 16) .. +3] and
-// B[4 (l / 16) .. +3][l % 16]; result lane l holds C[4 (l / 16) + r][l % 16],
-// r = 0..3.
+// the 64 x kTN tile as 2 x (kTN / 32) MFMA 16x16x32 blocks (one MFMA per
+// block and 32-deep k-step).
 template <int kTN, int kVA, int kVB>
 __global__ __launch_bounds__(256) void k_gemm(Gemm g) {
     constexpr int kNB = kTN / 32;
@@ -317,18 +327,16 @@ __global__ __launch_bounds__(256) void k_gemm(Gemm g) {
             ra.fetch(g.A, g.sam, g.sak, m0, g.M, k0 + kTK, ke, tid);
             rb.fetch(g.B, g.sbn, g.sbk, n0, g.N, k0 + kTK, ke, tid);
         }
-#pragma unroll
-        for (int kk = 0; kk < kTK; kk += 16) {
-            s16x4 a[2], b[kNB];
-            const int kq = kk + 4 * (lane >> 4);
+        static_assert(kTK == 32, "one 16x16x32 MFMA per block and k-step");
+        {
+            s16x8 a[2], b[kNB];
+            const int kq = 8 * (lane >> 4);
             for (int mb = 0; mb < 2; ++mb)
-                a[mb] = *(const s16x4*)&As[wm * 32 + mb * 16 + (lane & 15)][kq];
+                a[mb] = *(const s16x8*)&As[wm * 32 + mb * 16 + (lane & 15)][kq];
             for (int nb = 0; nb < kNB; ++nb)
-                b[nb] = *(const s16x4*)&Bs[wn * (kTN / 2) + nb * 16 + (lane & 15)][kq];
+                b[nb] = *(const s16x8*)&Bs[wn * (kTN / 2) + nb * 16 + (lane & 15)][kq];
             for (int mb = 0; mb < 2; ++mb)
-                for (int nb = 0; nb < kNB; ++nb)
-                    acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[mb], b[nb],
-                                                                            acc[mb][nb], 0, 0, 0);
+                for (int nb = 0; nb < kNB; ++nb) acc[mb][nb] = mfma32(a[mb], b[nb], acc[mb][nb]);
         }
         __syncthreads();
     }
@@ -585,14 +593,16 @@ void forward(const float* params, const uint16_t* wq, const uint16_t* feat, int 
 // HBM); weights come from L2 straight into the MFMA operand registers, the
 // next k-step's prefetched.  Same products in the same order and the same
 // epilogue rounding as the layered GEMMs.
-constexpr int kFR = 64, kXK = 112, kXP = kXK + 8, kHP = kHid + 8;
+constexpr int kFR = 64, kXK = 128, kXP = kXK + 8, kHP = kHid + 8;
+static_assert(kXK % 32 == 0 && kXK >= kIn, "layer-1 k padded to whole 32-deep steps");
 
-__device__ __forceinline__ s16x4 load_w4(const uint16_t* p, bool aligned8) {
-    if (aligned8) return *(const s16x4*)p;
-    const uint2 t = make_uint2(*(const uint32_t*)p, *(const uint32_t*)(p + 2));
-    s16x4 v;
-    __builtin_memcpy(&v, &t, 8);
-    return v;
+// eight consecutive bfloat16 weights (p 4-byte aligned; 16-byte loads when
+// the rows allow)
+__device__ __forceinline__ s16x8 load_w8(const uint16_t* p, bool aligned16) {
+    if (aligned16) return *(const s16x8*)p;
+    const uint4 t = make_uint4(*(const uint32_t*)p, *(const uint32_t*)(p + 2),
+                               *(const uint32_t*)(p + 4), *(const uint32_t*)(p + 6));
+    return __builtin_bit_cast(s16x8, t);
 }
 
 // Out[64][256] = relu(A[64][K] W^T + bias) in bfloat16; wave w computes
@@ -602,31 +612,29 @@ template <int K, int P>
 __device__ __forceinline__ void dense_relu(const uint16_t (*A)[P], const uint16_t* W, int ldw,
                                            const float* bias, uint16_t (*Out)[kHP], int w,
                                            int lane) {
-    const int j = lane & 15, kq = 4 * (lane >> 4);
-    const bool al = (ldw % 4) == 0;
+    const int j = lane & 15, kq = 8 * (lane >> 4);
+    const bool al = (ldw % 8) == 0;
     f32x4 acc[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
-    s16x4 bc[4], bn[4];
+    s16x8 bc[4], bn[4];
 #pragma unroll
-    for (int nb = 0; nb < 4; ++nb) bc[nb] = load_w4(W + (int64_t)(w * 64 + nb * 16 + j) * ldw + kq, al);
-    for (int k0 = 0; k0 < K; k0 += 16) {
-        if (k0 + 16 < K) {
+    for (int nb = 0; nb < 4; ++nb) bc[nb] = load_w8(W + (int64_t)(w * 64 + nb * 16 + j) * ldw + kq, al);
+    for (int k0 = 0; k0 < K; k0 += 32) {
+        if (k0 + 32 < K) {
 #pragma unroll
             for (int nb = 0; nb < 4; ++nb)
-                bn[nb] = load_w4(W + (int64_t)(w * 64 + nb * 16 + j) * ldw + k0 + 16 + kq, al);
+                bn[nb] = load_w8(W + (int64_t)(w * 64 + nb * 16 + j) * ldw + k0 + 32 + kq, al);
         }
-        s16x4 a[4];
+        s16x8 a[4];
 #pragma unroll
-        for (int mb = 0; mb < 4; ++mb) a[mb] = *(const s16x4*)&A[mb * 16 + j][k0 + kq];
+        for (int mb = 0; mb < 4; ++mb) a[mb] = *(const s16x8*)&A[mb * 16 + j][k0 + kq];
 #pragma unroll
         for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
-            for (int nb = 0; nb < 4; ++nb)
-                acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[mb], bc[nb], acc[mb][nb],
-                                                                        0, 0, 0);
+            for (int nb = 0; nb < 4; ++nb) acc[mb][nb] = mfma32(a[mb], bc[nb], acc[mb][nb]);
 #pragma unroll
         for (int nb = 0; nb < 4; ++nb) bc[nb] = bn[nb];
     }
@@ -666,13 +674,13 @@ __global__ __launch_bounds__(256, 2) void k_mlp_fused(const float* __restrict__ 
     __syncthreads();
     // output layer: wave w takes rows [16 w, 16 w + 16), columns 0..7 of a
     // 16-wide MFMA block
-    const int j = lane & 15, kq = 4 * (lane >> 4);
+    const int j = lane & 15, kq = 8 * (lane >> 4);
     f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < kHid; k0 += 16) {
-        const s16x4 a = *(const s16x4*)&H2[w * 16 + j][k0 + kq];
-        s16x4 b = s16x4{0, 0, 0, 0};
-        if (j < kOut) b = *(const s16x4*)(wq + kOffW3 + j * kHid + k0 + kq);
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+    for (int k0 = 0; k0 < kHid; k0 += 32) {
+        const s16x8 a = *(const s16x8*)&H2[w * 16 + j][k0 + kq];
+        s16x8 b = s16x8{0, 0, 0, 0, 0, 0, 0, 0};
+        if (j < kOut) b = *(const s16x8*)(wq + kOffW3 + j * kHid + k0 + kq);
+        acc = mfma32(a, b, acc);
     }
     if (j < kOut) {
         const float b3 = params[kOffB3 + j];
