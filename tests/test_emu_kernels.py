@@ -93,7 +93,7 @@ def _assert_hits(hits, ref):
 @pytest.mark.parametrize("name,shots,chunk", [("c1", 30, 1500), ("c3", 25, 30000)])
 def test_stream_kernels(emu, orc, kernel, name, shots, chunk):
     """Every clustering kernel of the stream path (the staged pair and each
-    fused variant: slot lists, forest and hook rounds, moments, staged hits
+    fused variant: slot lists, forest and atomic-minimum joins, moments, staged hits
     and their compaction; the routed variant's deferred segments and its
     persistent launch) on the small and the uneven-shot workloads, whole and
     in chunks."""
