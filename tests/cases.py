@@ -54,3 +54,33 @@ def big_component_packets(side=136, layers=2):
     return np.concatenate([synth.encode_tdc(trig[:1], [0]),
                            synth.encode_pixels(x, y, tot, t),
                            synth.encode_tdc(trig[1:], [1])])
+
+
+def shuffled_shapes_packets(seed, width=40):
+    """One shot of connected shapes whose pixels arrive in a random order, so
+    that the smallest-neighbour forest of each shape has many local minima
+    and trees must be joined many times over: a serpentine path one pixel
+    wide (every other row of a width x width box, joined at alternating
+    ends), a filled 20 x 20 square, a ring, and a few isolated pixels; times
+    spread over 100 ticks (every pair of neighbours within the window)."""
+    rng = np.random.default_rng(5000 + seed)
+    trig = np.array([1_000_000, 1_000_000 + synth.SHOT_PERIOD_TICKS])
+    pts = []
+    for r in range(0, width, 2):  # serpentine
+        pts += [(10 + c, 10 + r) for c in range(width)]
+        if r + 2 < width:
+            pts.append((10 + (width - 1 if (r // 2) % 2 == 0 else 0), 10 + r + 1))
+    pts += [(100 + c, 100 + r) for r in range(20) for c in range(20)]  # square
+    for a in range(0, 360, 3):  # ring of radius 15
+        p = (200 + int(round(15 * np.cos(np.radians(a)))), 60 + int(round(15 * np.sin(np.radians(a)))))
+        if p not in pts:
+            pts.append(p)
+    pts += [(2 * k, 250) for k in range(20)]  # isolated
+    xy = np.array(pts)
+    order = rng.permutation(len(xy))
+    x, y = xy[order, 0], xy[order, 1]
+    t = trig[0] + 1000 + rng.integers(0, 100, x.size)
+    tot = rng.integers(1, 600, x.size)
+    return np.concatenate([synth.encode_tdc(trig[:1], [0]),
+                           synth.encode_pixels(x, y, tot, t),
+                           synth.encode_tdc(trig[1:], [1])])

@@ -170,3 +170,21 @@ def test_stream_fused_capacity_paths(emu, orc, kernel, case):
     assert errs == ""
     assert st == 0
     _assert_hits(hits, ref)
+
+
+@pytest.mark.parametrize("kernel,seed", [(1, 0), (1, 1), (0, 2), (4, 3), (5, 4)])
+def test_stream_shuffled_shapes(emu, orc, kernel, seed):
+    """Connected shapes whose pixels arrive in a random order (a serpentine
+    path of 819 pixels, a 20 x 20 square, a ring): the smallest-neighbour
+    forest has many local minima, so the fused kernel's joins chain and
+    displace parents; every shape stays one hit under seeded interleavings
+    of the LDS atomics."""
+    from cases import shuffled_shapes_packets
+    pk = shuffled_shapes_packets(seed)
+    ref, _ = orc.run(pk)
+    assert sorted(ref["npix"])[-3:] == [88, 400, 819]
+    st, hits, errs = emu.run_stream(pk, 1 << 22, kernel=kernel, persistent=0, preempt=100,
+                                    seed=11 + seed)
+    assert errs == ""
+    assert st == 0
+    _assert_hits(hits, ref)

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import synth
-from cases import big_component_packets, many_components_packets
+from cases import big_component_packets, many_components_packets, shuffled_shapes_packets
 
 pytestmark = pytest.mark.gpu
 
@@ -186,6 +186,24 @@ def test_stream_many_components(tpx, orc, n_iso):
     pk = many_components_packets(n_iso)
     ref, _ = orc.run(pk)
     assert ref.size > 1024
+    for k in range(-1, tpx.kernel_count()):
+        h, _ = tpx.process_stream(pk, kernel=k, persistent=False)
+        assert_hits_match(h, ref)
+    h, _ = tpx.process_stream(pk, persistent=True)
+    assert_hits_match(h, ref)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_stream_shuffled_shapes(tpx, orc, seed):
+    """Connected shapes whose pixels arrive in a random order (a serpentine
+    path of 819 pixels, a 20 x 20 square, a ring of 88): the
+    smallest-neighbour forest has many local minima, so the clustering joins
+    chain and displace parents concurrently; each shape must stay one hit,
+    for every clustering kernel and the persistent launch."""
+    _say(f"shuffled shapes seed={seed}")
+    pk = shuffled_shapes_packets(seed)
+    ref, _ = orc.run(pk)
+    assert sorted(ref["npix"])[-3:] == [88, 400, 819]
     for k in range(-1, tpx.kernel_count()):
         h, _ = tpx.process_stream(pk, kernel=k, persistent=False)
         assert_hits_match(h, ref)
