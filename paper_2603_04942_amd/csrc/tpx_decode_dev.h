@@ -62,13 +62,44 @@ __device__ inline TileAcc shfl_up_acc(const TileAcc& v, int d) {
     return TileAcc{shfl_up_run(v.pix, d), shfl_up_run(v.tdc, d), __shfl_up(v.ntrig, d, 64)};
 }
 
-// Inclusive in-order fold over the lanes of a wave (Kogge-Stone).
+// Cross-lane moves of the data-parallel primitives (DPP) of GFX9: VALU
+// operand modifiers, no LDS round trip.  Controls: row_shr:n (from lane
+// l - n of the same 16-lane row), row_bcast:15 (lane 15 of the row before),
+// row_bcast:31 (lane 31), wave_shr:1 (lane l - 1).  A lane with no source,
+// or outside the row mask, reads 0, which is the empty run.
+constexpr int kDppRowShr = 0x110, kDppWaveShr1 = 0x138, kDppBcast15 = 0x142,
+              kDppBcast31 = 0x143;
+
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kCtrl, kRowMask, 0xf, true);
+}
+
+// A run moved across lanes; count and sum travel as 32 bits (within one
+// wave there are at most 64 x 16 words, so both fit).
+template <int kCtrl, int kRowMask = 0xf>
+__device__ __forceinline__ RunSum dpp_run(const RunSum& v) {
+    RunSum o;
+    o.first = ((uint64_t)dpp_u32<kCtrl, kRowMask>((uint32_t)(v.first >> 32)) << 32) |
+              dpp_u32<kCtrl, kRowMask>((uint32_t)v.first);
+    o.last = ((uint64_t)dpp_u32<kCtrl, kRowMask>((uint32_t)(v.last >> 32)) << 32) |
+             dpp_u32<kCtrl, kRowMask>((uint32_t)v.last);
+    o.sum = (int64_t)(int32_t)dpp_u32<kCtrl, kRowMask>((uint32_t)v.sum);
+    o.count = dpp_u32<kCtrl, kRowMask>((uint32_t)v.count);
+    return o;
+}
+
+// Inclusive in-order fold over the lanes of a wave: within each 16-lane row
+// by shifts of 1, 2, 4 and 8 lanes, then rows 1 and 3 take the end of rows 0
+// and 2, then rows 2 and 3 take the end of row 1 (the earlier part is always
+// the left operand, so the order is kept).  Every lane must be active.
 __device__ inline RunSum wave_run_inscan(RunSum v, uint64_t jump) {
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const RunSum o = shfl_up_run(v, d);
-        if ((int)__lane_id() >= d) v = run_combine(o, v, jump);
-    }
+    v = run_combine(dpp_run<kDppRowShr + 1>(v), v, jump);
+    v = run_combine(dpp_run<kDppRowShr + 2>(v), v, jump);
+    v = run_combine(dpp_run<kDppRowShr + 4>(v), v, jump);
+    v = run_combine(dpp_run<kDppRowShr + 8>(v), v, jump);
+    v = run_combine(dpp_run<kDppBcast15, 0xa>(v), v, jump);
+    v = run_combine(dpp_run<kDppBcast31, 0xc>(v), v, jump);
     return v;
 }
 
@@ -86,8 +117,7 @@ __device__ inline TileAcc wave_acc_inscan(TileAcc v, uint64_t jump) {
 template <int NW = kWaves>
 __device__ inline RunSum wg_run_exscan(RunSum v, RunSum* wbuf, uint64_t jump, RunSum* all) {
     const RunSum inc = wave_run_inscan(v, jump);
-    RunSum ex = shfl_up_run(inc, 1);
-    if (__lane_id() == 0) ex = run_empty();
+    const RunSum ex = dpp_run<kDppWaveShr1>(inc);  // lane 0 reads the empty run
     const int w = threadIdx.x >> 6;
     if (__lane_id() == 63) wbuf[w] = inc;
     __syncthreads();

@@ -168,6 +168,24 @@ void release_wave(int w, uintptr_t site) {
             case kShfl: f.wout = val(f.warg & 63); break;
             case kBallot: f.wout = ballot; break;
             case kFirst: f.wout = fibers[lo + first].wv; break;
+            case kDpp: {
+                const int c = f.warg;
+                int src = -1;
+                if (c > 0x110 && c <= 0x11F) {
+                    if ((l & 15) >= c - 0x110) src = l - (c - 0x110);
+                } else if (c == 0x138) {
+                    if (l >= 1) src = l - 1;
+                } else if (c == 0x142) {
+                    if (l >= 16) src = (l & ~15) - 1;
+                } else if (c == 0x143) {
+                    if (l >= 32) src = 31;
+                } else {
+                    add_error("unsupported DPP control " + std::to_string(c));
+                }
+                f.wout = (src >= 0 && ((active >> src) & 1)) ? (fibers[lo + src].wv & 0xFFFFFFFFull)
+                                                            : (1ull << 32);
+                break;
+            }
         }
         f.st = kReady;
     }

@@ -98,7 +98,7 @@ void maybe_preempt();
 void yield_sleep();
 void note_error(const char* what);
 
-enum { kShflXor = 0, kShflUp = 1, kShflDown = 2, kShfl = 3, kBallot = 4, kFirst = 5 };
+enum { kShflXor = 0, kShflUp = 1, kShflDown = 2, kShfl = 3, kBallot = 4, kFirst = 5, kDpp = 6 };
 
 template <class T>
 inline uint64_t to_bits(T v) {
@@ -167,6 +167,18 @@ __attribute__((noinline)) T emu_readfirstlane(T v) {
     return emu::from_bits<T>(emu::wave_op(EMU_SITE, emu::kFirst, emu::to_bits(v), 0));
 }
 #define __builtin_amdgcn_readfirstlane(v) emu_readfirstlane(v)
+// DPP move (the controls the kernels use: row_shr:n, wave_shr:1,
+// row_bcast:15, row_bcast:31); the wave op returns the source lane's value,
+// or bit 32 set when the lane has no active source lane
+__attribute__((noinline)) inline int emu_update_dpp(int old, int src, int ctrl, int row_mask,
+                                                    int bank_mask, bool bound_ctrl) {
+    const uint64_t r = emu::wave_op(EMU_SITE, emu::kDpp, (uint32_t)src, ctrl);
+    const unsigned l = __lane_id();
+    if (!((row_mask >> (l >> 4)) & 1) || !((bank_mask >> ((l >> 2) & 3)) & 1)) return old;
+    if (r >> 32) return bound_ctrl ? 0 : old;
+    return (int)(uint32_t)r;
+}
+#define __builtin_amdgcn_update_dpp(o, s, c, rm, bm, bc) emu_update_dpp(o, s, c, rm, bm, bc)
 #define __builtin_amdgcn_s_sleep(n) emu::yield_sleep()
 #define __builtin_amdgcn_wave_barrier() ((void)0)
 #define __builtin_nontemporal_load(p) (*(p))
