@@ -65,42 +65,52 @@ __device__ inline TileAcc shfl_up_acc(const TileAcc& v, int d) {
 // Cross-lane moves of the data-parallel primitives (DPP) of GFX9: VALU
 // operand modifiers, no LDS round trip.  Controls: row_shr:n (from lane
 // l - n of the same 16-lane row), row_bcast:15 (lane 15 of the row before),
-// row_bcast:31 (lane 31), wave_shr:1 (lane l - 1).  A lane with no source,
-// or outside the row mask, reads 0, which is the empty run.
+// row_bcast:31 (lane 31), wave_shr:1 (lane l - 1).
 constexpr int kDppRowShr = 0x110, kDppWaveShr1 = 0x138, kDppBcast15 = 0x142,
               kDppBcast31 = 0x143;
 
+// v of the source lane, or `fill` for a lane with no source or outside the
+// row mask
 template <int kCtrl, int kRowMask>
-__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
-    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kCtrl, kRowMask, 0xf, true);
+__device__ __forceinline__ uint32_t dpp_move(uint32_t v, uint32_t fill) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)fill, (int)v, kCtrl, kRowMask, 0xf, false);
 }
-
-// A run moved across lanes; count and sum travel as 32 bits (within one
-// wave there are at most 64 x 16 words, so both fit).
-template <int kCtrl, int kRowMask = 0xf>
-__device__ __forceinline__ RunSum dpp_run(const RunSum& v) {
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ uint64_t dpp_move(uint64_t v, uint64_t fill) {
+    return ((uint64_t)dpp_move<kCtrl, kRowMask>((uint32_t)(v >> 32), (uint32_t)(fill >> 32)) << 32) |
+           dpp_move<kCtrl, kRowMask>((uint32_t)v, (uint32_t)fill);
+}
+// A run moved across lanes (the fill is the empty run); count and sum travel
+// as 32 bits (within one wave there are at most 64 x 16 words, so both fit).
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ RunSum dpp_move(const RunSum& v, const RunSum&) {
     RunSum o;
-    o.first = ((uint64_t)dpp_u32<kCtrl, kRowMask>((uint32_t)(v.first >> 32)) << 32) |
-              dpp_u32<kCtrl, kRowMask>((uint32_t)v.first);
-    o.last = ((uint64_t)dpp_u32<kCtrl, kRowMask>((uint32_t)(v.last >> 32)) << 32) |
-             dpp_u32<kCtrl, kRowMask>((uint32_t)v.last);
-    o.sum = (int64_t)(int32_t)dpp_u32<kCtrl, kRowMask>((uint32_t)v.sum);
-    o.count = dpp_u32<kCtrl, kRowMask>((uint32_t)v.count);
+    o.first = dpp_move<kCtrl, kRowMask>(v.first, 0ull);
+    o.last = dpp_move<kCtrl, kRowMask>(v.last, 0ull);
+    o.sum = (int64_t)(int32_t)dpp_move<kCtrl, kRowMask>((uint32_t)v.sum, 0u);
+    o.count = dpp_move<kCtrl, kRowMask>((uint32_t)v.count, 0u);
     return o;
 }
 
-// Inclusive in-order fold over the lanes of a wave: within each 16-lane row
-// by shifts of 1, 2, 4 and 8 lanes, then rows 1 and 3 take the end of rows 0
-// and 2, then rows 2 and 3 take the end of row 1 (the earlier part is always
-// the left operand, so the order is kept).  Every lane must be active.
-__device__ inline RunSum wave_run_inscan(RunSum v, uint64_t jump) {
-    v = run_combine(dpp_run<kDppRowShr + 1>(v), v, jump);
-    v = run_combine(dpp_run<kDppRowShr + 2>(v), v, jump);
-    v = run_combine(dpp_run<kDppRowShr + 4>(v), v, jump);
-    v = run_combine(dpp_run<kDppRowShr + 8>(v), v, jump);
-    v = run_combine(dpp_run<kDppBcast15, 0xa>(v), v, jump);
-    v = run_combine(dpp_run<kDppBcast31, 0xc>(v), v, jump);
+// Inclusive in-order scan over the lanes of a wave; op(earlier, later), fill
+// its identity: within each 16-lane row by shifts of 1, 2, 4 and 8 lanes,
+// then rows 1 and 3 take the end of rows 0 and 2, then rows 2 and 3 take the
+// end of row 1 (the earlier part is always the left operand, so the order is
+// kept).  Every lane must be active; lane 63 ends with the whole wave.
+template <class T, class F>
+__device__ __forceinline__ T wave_inscan(T v, const T& fill, F op) {
+    v = op(dpp_move<kDppRowShr + 1, 0xf>(v, fill), v);
+    v = op(dpp_move<kDppRowShr + 2, 0xf>(v, fill), v);
+    v = op(dpp_move<kDppRowShr + 4, 0xf>(v, fill), v);
+    v = op(dpp_move<kDppRowShr + 8, 0xf>(v, fill), v);
+    v = op(dpp_move<kDppBcast15, 0xa>(v, fill), v);
+    v = op(dpp_move<kDppBcast31, 0xc>(v, fill), v);
     return v;
+}
+
+__device__ inline RunSum wave_run_inscan(RunSum v, uint64_t jump) {
+    return wave_inscan(v, run_empty(),
+                       [jump](const RunSum& a, const RunSum& b) { return run_combine(a, b, jump); });
 }
 
 __device__ inline TileAcc wave_acc_inscan(TileAcc v, uint64_t jump) {
@@ -117,7 +127,7 @@ __device__ inline TileAcc wave_acc_inscan(TileAcc v, uint64_t jump) {
 template <int NW = kWaves>
 __device__ inline RunSum wg_run_exscan(RunSum v, RunSum* wbuf, uint64_t jump, RunSum* all) {
     const RunSum inc = wave_run_inscan(v, jump);
-    const RunSum ex = dpp_run<kDppWaveShr1>(inc);  // lane 0 reads the empty run
+    const RunSum ex = dpp_move<kDppWaveShr1, 0xf>(inc, run_empty());  // lane 0: empty
     const int w = threadIdx.x >> 6;
     if (__lane_id() == 63) wbuf[w] = inc;
     __syncthreads();
@@ -432,43 +442,35 @@ __device__ __forceinline__ void assign_body(const AssignArgs& a, uint32_t tile_s
     // smallest kept shot, statistics
     const int w = threadIdx.x >> 6;
     const uint32_t m1 = nkeep ? last_s + 1 : 0;
-    uint32_t cinc = nkeep, minc = m1, fmin = nkeep ? first_s : kNo;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t oc = __shfl_up(cinc, d, 64), om = __shfl_up(minc, d, 64);
-        if ((int)__lane_id() >= d) {
-            cinc += oc;
-            minc = max(minc, om);
-        }
-        fmin = min(fmin, (uint32_t)__shfl_xor(fmin, d, 64));
-    }
+    // (inclusive scans over the wave; lane 63 holds the wave's totals)
+    auto add32 = [](uint32_t x, uint32_t y) { return x + y; };
+    auto max32 = [](uint32_t x, uint32_t y) { return max(x, y); };
+    auto min32 = [](uint32_t x, uint32_t y) { return min(x, y); };
+    auto add64 = [](uint64_t x, uint64_t y) { return x + y; };
+    auto max64 = [](uint64_t x, uint64_t y) { return max(x, y); };
+    const uint32_t cinc = wave_inscan(nkeep, 0u, add32), minc = wave_inscan(m1, 0u, max32);
+    const uint32_t fmin = wave_inscan(nkeep ? first_s : kNo, kNo, min32);
     // the seven per-thread counts (each <= 16) in 16-bit fields of two words
-    uint64_t st0 = (uint64_t)npix | ((uint64_t)nother << 16) | ((uint64_t)npre << 32) |
-                   ((uint64_t)ncut << 48);
-    uint64_t st1 = (uint64_t)nlate | ((uint64_t)fwd << 16) | ((uint64_t)back << 32);
-#pragma unroll
-    for (int d = 32; d > 0; d >>= 1) {
-        st0 += __shfl_xor(st0, d, 64);
-        st1 += __shfl_xor(st1, d, 64);
-    }
+    // (a wave's sums stay below 2^16 in every field)
+    const uint64_t st0 = wave_inscan((uint64_t)npix | ((uint64_t)nother << 16) |
+                                         ((uint64_t)npre << 32) | ((uint64_t)ncut << 48),
+                                     (uint64_t)0, add64);
+    const uint64_t st1 = wave_inscan((uint64_t)nlate | ((uint64_t)fwd << 16) | ((uint64_t)back << 32),
+                                     (uint64_t)0, add64);
     const uint32_t stat[7] = {(uint32_t)(st0 & 0xFFFF), (uint32_t)((st0 >> 16) & 0xFFFF),
                               (uint32_t)((st0 >> 32) & 0xFFFF), (uint32_t)(st0 >> 48),
                               (uint32_t)(st1 & 0xFFFF), (uint32_t)((st1 >> 16) & 0xFFFF),
                               (uint32_t)((st1 >> 32) & 0xFFFF)};
-    uint64_t tm = tmax1;
-    for (int d = 32; d > 0; d >>= 1) tm = max(tm, (uint64_t)__shfl_xor(tm, d, 64));
+    const uint64_t tm = wave_inscan(tmax1, (uint64_t)0, max64);
     if (__lane_id() == 63) {
         L.w_cnt[w] = cinc;
         L.w_max[w] = minc;
-    }
-    if (__lane_id() == 0) {
         L.w_min[w] = fmin;
 #pragma unroll
         for (int k = 0; k < 7; ++k) L.w_stat[w][k] = stat[k];
         L.w_stat[w][7] = tm;
     }
-    uint32_t mex_w = __shfl_up(minc, 1, 64);
-    if (__lane_id() == 0) mex_w = 0;
+    const uint32_t mex_w = dpp_move<kDppWaveShr1, 0xf>(minc, 0u);  // lane 0: 0
     __syncthreads();
     uint32_t tpre = cinc - nkeep, mex = mex_w, tile_keep = 0, tile_max1 = 0, tile_min = kNo;
 #pragma unroll
