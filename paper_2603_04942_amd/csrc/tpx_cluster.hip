@@ -1988,8 +1988,7 @@ union ChunkLds {
 __device__ inline TileAcc chunk_acc_exscan(TileAcc v, TileAcc* wbuf, uint64_t jump, TileAcc* all) {
     constexpr int NW = kChunkThreads / 64;
     const TileAcc inc = wave_acc_inscan(v, jump);
-    TileAcc ex = shfl_up_acc(inc, 1);
-    if (__lane_id() == 0) ex = acc_empty();
+    const TileAcc ex = wave_acc_shift1(inc);
     const int w = threadIdx.x >> 6;
     if (__lane_id() == 63) wbuf[w] = inc;
     __syncthreads();

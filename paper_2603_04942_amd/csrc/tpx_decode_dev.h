@@ -49,19 +49,6 @@ __device__ inline RunSum run_push(RunSum r, uint64_t raw, uint64_t jump) {
     return r;
 }
 
-__device__ inline RunSum shfl_up_run(const RunSum& v, int d) {
-    RunSum o;
-    o.first = __shfl_up(v.first, d, 64);
-    o.last = __shfl_up(v.last, d, 64);
-    o.sum = __shfl_up(v.sum, d, 64);
-    o.count = __shfl_up(v.count, d, 64);
-    return o;
-}
-
-__device__ inline TileAcc shfl_up_acc(const TileAcc& v, int d) {
-    return TileAcc{shfl_up_run(v.pix, d), shfl_up_run(v.tdc, d), __shfl_up(v.ntrig, d, 64)};
-}
-
 // Cross-lane moves of the data-parallel primitives (DPP) of GFX9: VALU
 // operand modifiers, no LDS round trip.  Controls: row_shr:n (from lane
 // l - n of the same 16-lane row), row_bcast:15 (lane 15 of the row before),
@@ -113,13 +100,30 @@ __device__ inline RunSum wave_run_inscan(RunSum v, uint64_t jump) {
                        [jump](const RunSum& a, const RunSum& b) { return run_combine(a, b, jump); });
 }
 
+// Tile and block summaries moved across lanes with every field at full
+// width (their counts are not bounded by one wave's words); the fill is the
+// empty summary.
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ TileAcc dpp_move(const TileAcc& v, const TileAcc&) {
+    auto run = [](const RunSum& r) {
+        RunSum o;
+        o.first = dpp_move<kCtrl, kRowMask>(r.first, (uint64_t)0);
+        o.last = dpp_move<kCtrl, kRowMask>(r.last, (uint64_t)0);
+        o.sum = (int64_t)dpp_move<kCtrl, kRowMask>((uint64_t)r.sum, (uint64_t)0);
+        o.count = dpp_move<kCtrl, kRowMask>(r.count, (uint64_t)0);
+        return o;
+    };
+    return TileAcc{run(v.pix), run(v.tdc), dpp_move<kCtrl, kRowMask>(v.ntrig, (uint64_t)0)};
+}
+
 __device__ inline TileAcc wave_acc_inscan(TileAcc v, uint64_t jump) {
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const TileAcc o = shfl_up_acc(v, d);
-        if ((int)__lane_id() >= d) v = acc_combine(o, v, jump);
-    }
-    return v;
+    return wave_inscan(v, acc_empty(),
+                       [jump](const TileAcc& a, const TileAcc& b) { return acc_combine(a, b, jump); });
+}
+
+// exclusive form of an inclusive scan: lane 0 gets the empty summary
+__device__ inline TileAcc wave_acc_shift1(const TileAcc& inc) {
+    return dpp_move<kDppWaveShr1, 0xf>(inc, acc_empty());
 }
 
 // Exclusive in-order fold of one RunSum per thread over a workgroup of NW
@@ -147,8 +151,7 @@ __device__ inline RunSum wg_run_exscan(RunSum v, RunSum* wbuf, uint64_t jump, Ru
 __device__ inline TileAcc wg1024_acc_exscan(TileAcc v, TileAcc* wbuf, uint64_t jump,
                                             TileAcc* all) {
     const TileAcc inc = wave_acc_inscan(v, jump);
-    TileAcc ex = shfl_up_acc(inc, 1);
-    if (__lane_id() == 0) ex = acc_empty();
+    const TileAcc ex = wave_acc_shift1(inc);
     const int w = threadIdx.x >> 6;
     if (__lane_id() == 63) wbuf[w] = inc;
     __syncthreads();
