@@ -1465,7 +1465,17 @@ __device__ __forceinline__ void fused_segment(const ClusterArgs& a, uint32_t k, 
         ncomp = fused_big<C, kNT>(a, lds, scan_tmp, goff, goff_lds, sg);
         global_acc = true;
     } else {
-        // 1. load, push on the slot lists
+        // 1. load, push on the slot lists (with few events per thread, the
+        // events are read while the image is cleared)
+        constexpr bool kEarly = kE <= 4;
+        uint64_t pkq[kEarly ? kE : 1];
+        if constexpr (kEarly) {
+#pragma unroll
+            for (int q = 0; q < kE; ++q) {
+                const uint32_t i = tid + q * kNT;
+                pkq[q] = i < n ? a.ev[e0 + i] : 0ull;
+            }
+        }
         for (int i = tid; i < C::kSlots / 8; i += kNT)
             ((uint4*)img)[i] = make_uint4(~0u, ~0u, ~0u, ~0u);
         __syncthreads();
@@ -1477,7 +1487,7 @@ __device__ __forceinline__ void fused_segment(const ClusterArgs& a, uint32_t k, 
                 const uint32_t g = goff_lds ? sg.g_lo + group_of(goff, 0, ng, (uint32_t)p)
                                             : group_of(a.grp_off, sg.g_lo, sg.g_hi, (uint32_t)p);
                 const uint32_t gs = (goff_lds ? goff[g - sg.g_lo] : a.grp_off[g]) - (uint32_t)e0;
-                const uint64_t pk = a.ev[p];
+                const uint64_t pk = kEarly ? pkq[kEarly ? q : 0] : a.ev[p];
                 const uint32_t x = ev_x(pk), y = ev_y(pk);
                 key[i] = (ev_t(pk) & 0xFFFFu) | (C::hi(gs, y) << C::kHShift);
                 xyt[i] = x | (y << 8) | (ev_tot(pk) << 16);
