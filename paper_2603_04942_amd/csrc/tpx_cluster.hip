@@ -1570,7 +1570,7 @@ __device__ __forceinline__ void fused_segment(const ClusterArgs& a, uint32_t k, 
             auto take = [&](uint32_t j, uint32_t kj, int s) {
                 if ((s < 4 || j < i) && kj + (s < 3 ? off_up : off_row) <= span) {
                     if (j < m) m = j;
-                    if (s < 4 && j > i) atomicMin(par + j, i);
+                    if (s < 4) atomicMin(par + j, i);  // no-op when j < i (par[j] <= j)
                     // shift register of 16-bit links: the newest at the
                     // bottom, the oldest dropped past kEd
 #pragma unroll
